@@ -1,0 +1,187 @@
+/*
+ * hpac.h -- C ABI of the MI355X (gfx950) approximated-region library.
+ *
+ * The library executes a data-parallel code region over n items on the GPU
+ * and applies one of the approximation techniques of HPAC-Offload
+ * (Fink, Parasyris, Georgakoudis, Menon, arXiv 2308.16877): input
+ * memoization (iACT), output memoization (TAF) and loop perforation, with the
+ * approximate-or-compute decision taken per hierarchy group (section 3.1.2),
+ * by default per 64-lane wavefront.
+ *
+ * Conventions shared by every entry point:
+ *  - All column pointers are DEVICE pointers owned by the caller.  The
+ *    library never allocates, frees or retains device memory; its only state
+ *    is in registers and LDS for the duration of one launch (section 3.1.1).
+ *  - Calls are asynchronous on `stream` (a hipStream_t; NULL = the null
+ *    stream).  Nothing is synchronised; a kernel fault surfaces at the
+ *    caller's next synchronisation of that stream.
+ *  - Every entry point returns an hpac_status.  HPAC_EINVAL is returned
+ *    before any HIP call is made, so argument checking works on a host
+ *    without a GPU.  hpac_last_error() returns a thread-local message for the
+ *    last non-OK status of the calling thread.
+ *  - No C++ exception crosses this interface.
+ *  - Item -> lane mapping (sections 3.1.3, 3.3; items per thread, Table 2):
+ *    L = 64 * ceil(ceil(n / items_per_lane) / 64) logical lanes; lane l at
+ *    grid-stride step k (0 <= k < items_per_lane) owns item i = l + k * L and
+ *    is active iff i < n.  Wave w holds lanes 64w .. 64w + 63.  The
+ *    approximation state (tables, windows, countdowns) of a lane, wave or
+ *    block lives for one launch and evolves over its steps k in order, so
+ *    results depend on items_per_lane (and, at block level, on block_size).
+ *  - Majority rule (section 3.3): a group approximates iff more than half of
+ *    its active lanes meet the technique's criterion; a tie computes.
+ *  - A threshold (or perforation parameter) of 0 reproduces the exact
+ *    region bit for bit.
+ */
+#ifndef HPAC_H
+#define HPAC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hpac_status;
+#define HPAC_OK 0
+#define HPAC_EINVAL (-1)       /* an argument is out of range or NULL       */
+#define HPAC_EUNSUPPORTED (-2) /* valid request this build does not provide */
+#define HPAC_EHIP (-3)         /* the HIP runtime reported an error         */
+
+/* Regions.  Inputs and outputs are structure-of-arrays columns of n
+ * elements (the column-major, stride-n array sections of section 3.2).
+ *
+ * HPAC_REGION_BS_PRICE: European call and put under Black-Scholes-Merton
+ *   (the paper's Black-Scholes benchmark, section 4 and Table 1).
+ *   in  (5): S spot, K strike, T years to expiry, r riskless rate, v volatility
+ *   out (2): call, put.  Domain: S, K, T, v > 0.
+ * HPAC_REGION_BS_PRICE_GRAD: the same prices plus their Jacobian.
+ *   in  (5): as above.  out (12): call, put, then dC/d(S, K, T, r, v) and
+ *   dP/d(S, K, T, r, v).  Under iACT the memoized outputs are all 12
+ *   columns, so a reused entry also reuses its gradients. */
+#define HPAC_REGION_BS_PRICE 0
+#define HPAC_REGION_BS_PRICE_GRAD 1
+
+/* Element type of every column of a call. */
+#define HPAC_F32 0
+
+/* Decision hierarchy (section 3.1.2, the level clause of section 3.2). */
+#define HPAC_LEVEL_THREAD 0 /* each lane decides alone                     */
+#define HPAC_LEVEL_WAVE 1   /* 64-lane wavefront decides by majority       */
+#define HPAC_LEVEL_BLOCK 2  /* the workgroup decides by majority           */
+
+/* Perforation kinds (section 2.3; runtime in section 3.3). */
+#define HPAC_PERFO_SMALL 0 /* skip step k iff (k + offset) mod M == M - 1 */
+#define HPAC_PERFO_LARGE 1 /* run step k only iff (k + offset) mod M == 0 */
+#define HPAC_PERFO_INI 2   /* skip items i < floor(p * n / 100)            */
+#define HPAC_PERFO_FINI 3  /* skip items i >= n - floor(p * n / 100)       */
+
+/* Counters, accumulated with atomics when hpac_region_io.counters != NULL
+ * (the caller zeroes them): */
+#define HPAC_CNT_LANE_STEPS 0        /* items visited (active lane-steps)  */
+#define HPAC_CNT_APPROX_LANE_STEPS 1 /* items approximated or skipped      */
+#define HPAC_CNT_APPROX_WAVE_STEPS 2 /* wave-steps taken approximately     */
+#define HPAC_CNT_WAVE_STEPS 3        /* wave-steps with an active lane     */
+#define HPAC_NUM_COUNTERS 4
+
+/* Trace record, one uint32 per (wave w, step k) at trace[w * ipt + k] when
+ * hpac_region_io.trace != NULL (hpac_trace_entries() entries):
+ *   bits  0..6   lanes whose criterion held at this step's vote
+ *   bits  8..14  lanes that took the approximate path
+ *   bits 16..21  iACT writer lane (table 0 of the wave); bit 22 set if valid
+ *   bit  24      the wave's decision was approximate (perforation: skipped)
+ *   bit  25      a vote was taken at this step
+ *   bit  31      the wave had an active lane at this step (else all zero)  */
+#define HPAC_TRACE_VOTES(t) ((t) & 0x7Fu)
+#define HPAC_TRACE_NAPPROX(t) (((t) >> 8) & 0x7Fu)
+#define HPAC_TRACE_WRITER(t) (((t) >> 16) & 0x3Fu)
+#define HPAC_TRACE_WRITER_VALID(t) (((t) >> 22) & 1u)
+#define HPAC_TRACE_APPROX(t) (((t) >> 24) & 1u)
+#define HPAC_TRACE_VOTED(t) (((t) >> 25) & 1u)
+#define HPAC_TRACE_ACTIVE(t) (((t) >> 31) & 1u)
+
+/* One launch of a region over n items. */
+typedef struct hpac_region_io {
+  int32_t region;          /* HPAC_REGION_*                                  */
+  int32_t dtype;           /* HPAC_F32                                       */
+  int64_t n;               /* items, 0 <= n <= 2^40; n == 0 launches nothing */
+  const void *const *in;   /* host array of n_in device column pointers     */
+  int32_t n_in;            /* must equal the region's input count           */
+  void *const *out;        /* host array of n_out device column pointers    */
+  int32_t n_out;           /* must equal the region's output count          */
+  int32_t items_per_lane;  /* 1 .. 65536                                     */
+  int32_t block_size;      /* workgroup lanes: 64, 128, 192 or 256; 0 = 256  */
+  void *stream;            /* hipStream_t; NULL = null stream                */
+  uint32_t *trace;         /* optional device buffer, see above              */
+  uint64_t *counters;      /* optional device uint64[HPAC_NUM_COUNTERS]      */
+} hpac_region_io;
+
+/* Exact region: every item is evaluated.  Outputs are bitwise those that
+ * every technique produces on its accurate path. */
+hpac_status hpac_exact(const hpac_region_io *io);
+
+/* iACT input memoization (sections 2.3, 3.1.4, 3.2, 3.3).
+ * table_size: entries per table, 1..32 (the tSize clause argument).
+ * threshold:  Euclidean distance threshold over the region's inputs in
+ *             their own units, finite, >= 0 (FP32, as the 0.5f of the
+ *             clause).  A lane's criterion: its table is non-empty and the
+ *             squared distance to its nearest entry, computed in FP32 as
+ *             t0*t0 then fma(tj, tj, acc) for j = 1.., with tj = x_j - e_j,
+ *             is below threshold*threshold (FP32).  Nearest: lowest slot
+ *             among equal distances.
+ * tables_per_wave: tables shared by 64 / tables_per_wave consecutive lanes
+ *             (the tPerWarp clause argument); must divide 64.
+ * level:      HPAC_LEVEL_*.
+ * Approximate lanes return their nearest entry's outputs without evaluating
+ * the region.  Write phase: in each table, among its lanes that evaluated
+ * the region this step, the one whose nearest-entry distance is largest
+ * (infinite for an empty table; lowest lane on ties) stores its inputs and
+ * outputs at slot (insertions mod table_size), round robin.  Tables start
+ * empty at every launch. */
+hpac_status hpac_iact(const hpac_region_io *io, int32_t table_size, float threshold,
+                      int32_t tables_per_wave, int32_t level);
+
+/* TAF output memoization (sections 2.3, 3.1.3, 3.2, 3.3).
+ * history_size:    window of a lane's last accurate outputs, 1..8 (hSize).
+ * prediction_size: steps approximated after a passing vote, >= 1 (pSize).
+ * rsd_threshold:   finite, >= 0 (FP32).  After each accurate step that
+ *   leaves the window full, a lane's criterion is RSD < rsd_threshold, with
+ *   RSD = sigma/|mu| (population) maximised over the region's outputs,
+ *   RSD = 0 when sigma = 0 and +inf when mu = 0 < sigma, evaluated in FP64
+ *   as var == 0 ? threshold > 0 : var < threshold^2 * mu^2.  A passing group
+ *   approximates its next prediction_size steps: each active lane writes its
+ *   last accurate output and reads no input.  The window slides over
+ *   accurate steps only and is never reset within a launch. */
+hpac_status hpac_taf(const hpac_region_io *io, int32_t history_size, int32_t prediction_size,
+                     float rsd_threshold, int32_t level);
+
+/* Herded loop perforation (sections 2.3, 3.1.5, 3.3): every lane drops the
+ * same steps, so control flow stays uniform across each wave.
+ * kind: HPAC_PERFO_*.  param: M >= 0 for SMALL/LARGE, percent 0..100 for
+ * INI/FINI; 0 = no perforation.  offset >= 0 is added to the step index.
+ * A dropped item reads no input and writes no output (its output columns
+ * keep their previous contents). */
+hpac_status hpac_perfo(const hpac_region_io *io, int32_t kind, int32_t param, int32_t offset);
+
+/* Number of logical lanes L for n items at items_per_lane (see above);
+ * -1 on invalid arguments. */
+int64_t hpac_num_lanes(int64_t n, int32_t items_per_lane);
+
+/* Entries a trace buffer needs: (L / 64) * items_per_lane; -1 if invalid. */
+int64_t hpac_trace_entries(int64_t n, int32_t items_per_lane);
+
+/* Measurement helper, not part of the method: copies `bytes` (a multiple of
+ * 16) from src to dst with a plain streaming kernel on `stream`.  Used to
+ * calibrate hardware byte counters against a transfer of known size. */
+hpac_status hpac_probe_copy(const void *src, void *dst, int64_t bytes, void *stream);
+
+/* Thread-local message describing the last non-OK status; never NULL. */
+const char *hpac_last_error(void);
+
+/* ABI version of this header: 1. */
+int32_t hpac_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HPAC_H */

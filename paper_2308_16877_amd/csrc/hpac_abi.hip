@@ -1,0 +1,186 @@
+// C ABI of the approximated-region library: argument checking (no HIP call
+// is made before all arguments pass), dispatch to the kernel launchers, and
+// the thread-local error message.  Declarations and semantics: hpac.h.
+#include "../../include/hpac.h"
+#include "launch.hpp"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+namespace {
+
+thread_local char g_err[512] = "no error";
+
+hpac_status fail(hpac_status s, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+struct RegionShape {
+  int n_in, n_out;
+};
+
+bool region_shape(int region, RegionShape *s) {
+  switch (region) {
+    case HPAC_REGION_BS_PRICE: *s = {5, 2}; return true;
+    case HPAC_REGION_BS_PRICE_GRAD: *s = {5, 12}; return true;
+    default: return false;
+  }
+}
+
+constexpr int64_t kMaxItems = (int64_t)1 << 40;
+constexpr int32_t kMaxIpt = 65536;
+
+int64_t num_lanes(int64_t n, int32_t ipt) {
+  const int64_t per = (n + ipt - 1) / ipt;
+  return ((per + 63) / 64) * 64;
+}
+
+// Validates the launch description and fills the kernel arguments.
+hpac_status check_io(const char *fn, const hpac_region_io *io, hpac::KArgs *a, hpac::LaunchCfg *c) {
+  if (!io) return fail(HPAC_EINVAL, "%s: io is NULL", fn);
+  RegionShape rs;
+  if (!region_shape(io->region, &rs)) return fail(HPAC_EINVAL, "%s: unknown region %d", fn, io->region);
+  if (io->dtype != HPAC_F32) return fail(HPAC_EUNSUPPORTED, "%s: dtype %d not provided (only HPAC_F32)", fn, io->dtype);
+  if (io->n < 0 || io->n > kMaxItems) return fail(HPAC_EINVAL, "%s: n = %lld out of range [0, 2^40]", fn, (long long)io->n);
+  if (io->n_in != rs.n_in || io->n_out != rs.n_out)
+    return fail(HPAC_EINVAL, "%s: region %d takes %d inputs and %d outputs, got %d and %d", fn, io->region, rs.n_in,
+                rs.n_out, io->n_in, io->n_out);
+  if (io->items_per_lane < 1 || io->items_per_lane > kMaxIpt)
+    return fail(HPAC_EINVAL, "%s: items_per_lane = %d out of range [1, %d]", fn, io->items_per_lane, kMaxIpt);
+  const int block = io->block_size == 0 ? 256 : io->block_size;
+  if (block < 64 || block > 256 || block % 64)
+    return fail(HPAC_EINVAL, "%s: block_size = %d must be 64, 128, 192 or 256", fn, io->block_size);
+  if (io->n > 0) {
+    if (!io->in || !io->out) return fail(HPAC_EINVAL, "%s: NULL column array", fn);
+    for (int j = 0; j < rs.n_in; ++j) {
+      if (!io->in[j]) return fail(HPAC_EINVAL, "%s: input column %d is NULL", fn, j);
+      if ((uintptr_t)io->in[j] % 4) return fail(HPAC_EINVAL, "%s: input column %d is not 4-byte aligned", fn, j);
+    }
+    for (int o = 0; o < rs.n_out; ++o) {
+      if (!io->out[o]) return fail(HPAC_EINVAL, "%s: output column %d is NULL", fn, o);
+      if ((uintptr_t)io->out[o] % 4) return fail(HPAC_EINVAL, "%s: output column %d is not 4-byte aligned", fn, o);
+    }
+  }
+  if ((uintptr_t)io->trace % 4) return fail(HPAC_EINVAL, "%s: trace is not 4-byte aligned", fn);
+  if ((uintptr_t)io->counters % 8) return fail(HPAC_EINVAL, "%s: counters are not 8-byte aligned", fn);
+  for (int j = 0; j < hpac::kMaxIn; ++j) a->in[j] = j < rs.n_in && io->n > 0 ? (const float *)io->in[j] : nullptr;
+  for (int o = 0; o < hpac::kMaxOut; ++o) a->out[o] = o < rs.n_out && io->n > 0 ? (float *)io->out[o] : nullptr;
+  a->n = io->n;
+  a->ipt = io->items_per_lane;
+  a->L = num_lanes(io->n, io->items_per_lane);
+  a->trace = io->trace;
+  a->counters = (unsigned long long *)io->counters;
+  c->region = io->region;
+  c->block = block;
+  c->stream = (hipStream_t)io->stream;
+  return HPAC_OK;
+}
+
+hpac_status check_level(const char *fn, int32_t level) {
+  if (level != HPAC_LEVEL_THREAD && level != HPAC_LEVEL_WAVE && level != HPAC_LEVEL_BLOCK)
+    return fail(HPAC_EINVAL, "%s: unknown level %d", fn, level);
+  return HPAC_OK;
+}
+
+hpac_status check_threshold(const char *fn, float t) {
+  if (!(t >= 0.0f) || !isfinite(t)) return fail(HPAC_EINVAL, "%s: threshold must be finite and >= 0", fn);
+  return HPAC_OK;
+}
+
+hpac_status hip_status(const char *fn, hipError_t e) {
+  if (e != hipSuccess) return fail(HPAC_EHIP, "%s: %s", fn, hipGetErrorString(e));
+  return HPAC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t hpac_abi_version(void) { return 1; }
+
+const char *hpac_last_error(void) { return g_err; }
+
+int64_t hpac_num_lanes(int64_t n, int32_t items_per_lane) {
+  if (n < 0 || n > kMaxItems || items_per_lane < 1 || items_per_lane > kMaxIpt) return -1;
+  return num_lanes(n, items_per_lane);
+}
+
+int64_t hpac_trace_entries(int64_t n, int32_t items_per_lane) {
+  const int64_t L = hpac_num_lanes(n, items_per_lane);
+  return L < 0 ? -1 : (L / 64) * items_per_lane;
+}
+
+hpac_status hpac_exact(const hpac_region_io *io) {
+  hpac::KArgs a;
+  hpac::LaunchCfg c;
+  hpac_status s = check_io("hpac_exact", io, &a, &c);
+  if (s != HPAC_OK || a.n == 0) return s;
+  return hip_status("hpac_exact", hpac::launch_exact(c, a));
+}
+
+hpac_status hpac_iact(const hpac_region_io *io, int32_t table_size, float threshold, int32_t tables_per_wave,
+                      int32_t level) {
+  const char *fn = "hpac_iact";
+  hpac::KArgs a;
+  hpac::LaunchCfg c;
+  hpac_status s = check_io(fn, io, &a, &c);
+  if (s != HPAC_OK) return s;
+  if (table_size < 1 || table_size > 32) return fail(HPAC_EINVAL, "%s: table_size = %d out of range [1, 32]", fn, table_size);
+  if ((s = check_threshold(fn, threshold)) != HPAC_OK) return s;
+  if (tables_per_wave < 1 || tables_per_wave > 64 || 64 % tables_per_wave)
+    return fail(HPAC_EINVAL, "%s: tables_per_wave = %d must divide 64", fn, tables_per_wave);
+  if ((s = check_level(fn, level)) != HPAC_OK) return s;
+  const int64_t lds = hpac::iact_lds_bytes(c.region, c.block, table_size, tables_per_wave);
+  if (lds > 65536)
+    return fail(HPAC_EUNSUPPORTED, "%s: tables need %lld bytes of LDS per workgroup (limit 65536); use a smaller block",
+                fn, (long long)lds);
+  if (a.n == 0) return HPAC_OK;
+  return hip_status(fn, hpac::launch_iact(c, a, level, table_size, threshold, tables_per_wave));
+}
+
+hpac_status hpac_taf(const hpac_region_io *io, int32_t history_size, int32_t prediction_size, float rsd_threshold,
+                     int32_t level) {
+  const char *fn = "hpac_taf";
+  hpac::KArgs a;
+  hpac::LaunchCfg c;
+  hpac_status s = check_io(fn, io, &a, &c);
+  if (s != HPAC_OK) return s;
+  if (history_size < 1 || history_size > 8)
+    return fail(HPAC_EINVAL, "%s: history_size = %d out of range [1, 8]", fn, history_size);
+  if (prediction_size < 1) return fail(HPAC_EINVAL, "%s: prediction_size = %d must be >= 1", fn, prediction_size);
+  if ((s = check_threshold(fn, rsd_threshold)) != HPAC_OK) return s;
+  if ((s = check_level(fn, level)) != HPAC_OK) return s;
+  if (a.n == 0) return HPAC_OK;
+  return hip_status(fn, hpac::launch_taf(c, a, level, history_size, prediction_size, rsd_threshold));
+}
+
+hpac_status hpac_perfo(const hpac_region_io *io, int32_t kind, int32_t param, int32_t offset) {
+  const char *fn = "hpac_perfo";
+  hpac::KArgs a;
+  hpac::LaunchCfg c;
+  hpac_status s = check_io(fn, io, &a, &c);
+  if (s != HPAC_OK) return s;
+  if (kind < HPAC_PERFO_SMALL || kind > HPAC_PERFO_FINI) return fail(HPAC_EINVAL, "%s: unknown kind %d", fn, kind);
+  if (param < 0) return fail(HPAC_EINVAL, "%s: param = %d must be >= 0", fn, param);
+  if ((kind == HPAC_PERFO_INI || kind == HPAC_PERFO_FINI) && param > 100)
+    return fail(HPAC_EINVAL, "%s: percentage %d out of range [0, 100]", fn, param);
+  if (offset < 0) return fail(HPAC_EINVAL, "%s: offset = %d must be >= 0", fn, offset);
+  if (a.n == 0) return HPAC_OK;
+  return hip_status(fn, hpac::launch_perfo(c, a, kind, param, offset));
+}
+
+hpac_status hpac_probe_copy(const void *src, void *dst, int64_t bytes, void *stream) {
+  const char *fn = "hpac_probe_copy";
+  if (bytes < 0 || bytes % 16) return fail(HPAC_EINVAL, "%s: bytes must be a non-negative multiple of 16", fn);
+  if (bytes > 0 && (!src || !dst)) return fail(HPAC_EINVAL, "%s: NULL buffer", fn);
+  if ((uintptr_t)src % 16 || (uintptr_t)dst % 16) return fail(HPAC_EINVAL, "%s: buffers must be 16-byte aligned", fn);
+  if (bytes == 0) return HPAC_OK;
+  return hip_status(fn, hpac::launch_copy(src, dst, bytes, (hipStream_t)stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,187 @@
+"""Python binding of libhpac.so: argument marshalling only.
+
+Every function here has the name of the C entry point it calls (include/
+hpac.h) and forwards device pointers and sizes; all work runs in the HIP
+kernels.  Columns may be torch tensors on the GPU (float32, contiguous, one
+dimension) or raw device addresses (ints).  The stream defaults to torch's
+current stream.  A missing library raises; there is no fallback path.
+"""
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libhpac.so")
+
+HPAC_OK, HPAC_EINVAL, HPAC_EUNSUPPORTED, HPAC_EHIP = 0, -1, -2, -3
+REGION_BS_PRICE, REGION_BS_PRICE_GRAD = 0, 1
+REGION_SHAPE = {REGION_BS_PRICE: (5, 2), REGION_BS_PRICE_GRAD: (5, 12)}
+F32 = 0
+LEVEL_THREAD, LEVEL_WAVE, LEVEL_BLOCK = 0, 1, 2
+LEVELS = {"thread": LEVEL_THREAD, "wave": LEVEL_WAVE, "warp": LEVEL_WAVE, "block": LEVEL_BLOCK, "team": LEVEL_BLOCK}
+PERFO_SMALL, PERFO_LARGE, PERFO_INI, PERFO_FINI = 0, 1, 2, 3
+PERFO_KINDS = {"small": PERFO_SMALL, "large": PERFO_LARGE, "ini": PERFO_INI, "fini": PERFO_FINI}
+NUM_COUNTERS = 4
+
+
+class hpac_region_io(ctypes.Structure):
+    _fields_ = [
+        ("region", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("n", ctypes.c_int64),
+        ("in_", ctypes.POINTER(ctypes.c_void_p)),
+        ("n_in", ctypes.c_int32),
+        ("out", ctypes.POINTER(ctypes.c_void_p)),
+        ("n_out", ctypes.c_int32),
+        ("items_per_lane", ctypes.c_int32),
+        ("block_size", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+        ("trace", ctypes.c_void_p),
+        ("counters", ctypes.c_void_p),
+    ]
+
+
+class HpacError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s (status %d)" % (message, status))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libhpac.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libhpac.so is not built; run `python -m paper_2308_16877_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    IO = ctypes.POINTER(hpac_region_io)
+    i32, i64, f32, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_void_p
+    L.hpac_exact.argtypes = [IO]
+    L.hpac_iact.argtypes = [IO, i32, f32, i32, i32]
+    L.hpac_taf.argtypes = [IO, i32, i32, f32, i32]
+    L.hpac_perfo.argtypes = [IO, i32, i32, i32]
+    L.hpac_probe_copy.argtypes = [vp, vp, i64, vp]
+    for f in (L.hpac_exact, L.hpac_iact, L.hpac_taf, L.hpac_perfo, L.hpac_probe_copy):
+        f.restype = i32
+    L.hpac_num_lanes.argtypes = [i64, i32]
+    L.hpac_num_lanes.restype = i64
+    L.hpac_trace_entries.argtypes = [i64, i32]
+    L.hpac_trace_entries.restype = i64
+    L.hpac_last_error.argtypes = []
+    L.hpac_last_error.restype = ctypes.c_char_p
+    L.hpac_abi_version.argtypes = []
+    L.hpac_abi_version.restype = i32
+    _lib = L
+    return L
+
+
+def _addr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    if not t.is_cuda:
+        raise ValueError("columns must be GPU tensors")
+    return t.data_ptr()
+
+
+def _check_column(t, n):
+    if isinstance(t, int):
+        return
+    import torch
+    if t.dtype != torch.float32 or t.dim() != 1 or not t.is_contiguous() or t.numel() != n:
+        raise ValueError("each column must be a contiguous 1-D float32 tensor of n elements")
+
+
+def _stream(stream, cols):
+    if stream is not None:
+        return stream if isinstance(stream, int) else stream.cuda_stream
+    if any(not isinstance(c, int) for c in cols):
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return None
+
+
+def make_io(inputs, outputs, n=None, region=None, items_per_lane=1, block_size=0,
+            stream=None, trace=None, counters=None):
+    """Build the hpac_region_io descriptor (the arrays it points to are kept
+    alive on the returned object)."""
+    inputs, outputs = list(inputs), list(outputs)
+    if region is None:
+        region = REGION_BS_PRICE if len(outputs) == 2 else REGION_BS_PRICE_GRAD
+    if n is None:
+        n = outputs[0].numel()
+    for c in inputs + outputs:
+        _check_column(c, n)
+    ins = (ctypes.c_void_p * max(len(inputs), 1))(*[_addr(c) for c in inputs])
+    outs = (ctypes.c_void_p * max(len(outputs), 1))(*[_addr(c) for c in outputs])
+    io = hpac_region_io(region, F32, n, ctypes.cast(ins, ctypes.POINTER(ctypes.c_void_p)), len(inputs),
+                        ctypes.cast(outs, ctypes.POINTER(ctypes.c_void_p)), len(outputs),
+                        items_per_lane, block_size, _stream(stream, inputs + outputs),
+                        _addr(trace), _addr(counters))
+    io._keep = (ins, outs)
+    return io
+
+
+def _call(name, status):
+    if status != HPAC_OK:
+        raise HpacError(status, "%s: %s" % (name, lib().hpac_last_error().decode()))
+
+
+def _level(level):
+    return LEVELS[level] if isinstance(level, str) else int(level)
+
+
+def hpac_exact(inputs, outputs, **kw):
+    io = make_io(inputs, outputs, **kw)
+    _call("hpac_exact", lib().hpac_exact(ctypes.byref(io)))
+
+
+def hpac_iact(inputs, outputs, table_size, threshold, tables_per_wave=1, level="wave", **kw):
+    io = make_io(inputs, outputs, **kw)
+    _call("hpac_iact", lib().hpac_iact(ctypes.byref(io), table_size, threshold, tables_per_wave, _level(level)))
+
+
+def hpac_taf(inputs, outputs, history_size, prediction_size, rsd_threshold, level="wave", **kw):
+    io = make_io(inputs, outputs, **kw)
+    _call("hpac_taf", lib().hpac_taf(ctypes.byref(io), history_size, prediction_size, rsd_threshold, _level(level)))
+
+
+def hpac_perfo(inputs, outputs, kind, param, offset=0, **kw):
+    io = make_io(inputs, outputs, **kw)
+    k = PERFO_KINDS[kind] if isinstance(kind, str) else int(kind)
+    _call("hpac_perfo", lib().hpac_perfo(ctypes.byref(io), k, param, offset))
+
+
+def hpac_probe_copy(src, dst, nbytes, stream=None):
+    _call("hpac_probe_copy", lib().hpac_probe_copy(_addr(src), _addr(dst), nbytes, _stream(stream, [src, dst])))
+
+
+def hpac_num_lanes(n, items_per_lane):
+    return lib().hpac_num_lanes(n, items_per_lane)
+
+
+def hpac_trace_entries(n, items_per_lane):
+    return lib().hpac_trace_entries(n, items_per_lane)
+
+
+def hpac_last_error():
+    return lib().hpac_last_error().decode()
+
+
+def hpac_abi_version():
+    return lib().hpac_abi_version()
+
+
+# trace word fields (hpac.h)
+def trace_fields(t):
+    """Decode a numpy/torch int array of trace words into a dict of arrays."""
+    import numpy as np
+    t = np.asarray(t).astype(np.uint64)
+    return dict(votes=(t & 0x7F).astype(np.int64), napprox=((t >> 8) & 0x7F).astype(np.int64),
+                writer=((t >> 16) & 0x3F).astype(np.int64), writer_valid=((t >> 22) & 1).astype(bool),
+                approx=((t >> 24) & 1).astype(bool), voted=((t >> 25) & 1).astype(bool),
+                active=((t >> 31) & 1).astype(bool))

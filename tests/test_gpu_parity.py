@@ -1,0 +1,288 @@
+"""GPU parity: every entry point, called through the C ABI on seeded inputs,
+against the CPU oracle.
+
+Bars:
+ - outputs within 1e-5 of the scale |S N(d1)| + |K e^{-rT} N(d2)| (and the
+   put's analogue) of the item whose region evaluation produced them;
+ - iACT decisions, votes and writers bit-exact (both sides evaluate the
+   squared distance in FP32 with the same rounding sequence);
+ - TAF decisions equal except at steps the oracle marks fragile (an RSD
+   within the band of the threshold that could flip the majority), where
+   the rest of that wave is excluded; at least 99.99% agree;
+ - perforation decisions bit-exact, dropped items untouched;
+ - MAPE against the FP64 exact prices within 1e-4 of the oracle's;
+ - threshold or rate 0 reproduces hpac_exact bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import (SENTINEL, check_outputs, compare_decisions, mape_pair, run, say, to_dev, trace_dec)
+from paper_2308_16877_amd import hpac, inputs
+
+pytestmark = pytest.mark.gpu
+
+LEVEL_GROUP = {"thread": 1, "wave": 64, "block": None}
+
+
+def group_of(level, block_size):
+    return block_size if level == "block" else LEVEL_GROUP[level]
+
+
+def exact_ref(x):
+    C, P, sC, sP = oracle.bs_price(*x)
+    return np.stack([C, P]), np.stack([sC, sP])
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    hpac.lib()  # fails loudly if the library is missing
+    say("device:", torch.cuda.get_device_name(0))
+
+
+# ------------------------------------------------------------------- exact
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 1000, 4099, 65536])
+@pytest.mark.parametrize("ipt", [1, 3, 16])
+def test_exact_matches_oracle(n, ipt):
+    say("exact n=%d ipt=%d" % (n, ipt))
+    x = inputs.portfolio(n, 1024)
+    y, t, cnt = run("exact", to_dev(x), 2, ipt)
+    ref, scale = exact_ref(x)
+    check_outputs(y, ref, scale, what="exact")
+    assert cnt[0] == n
+
+
+def test_exact_full_box_and_extremes():
+    # uniform over the box plus its corners and deep in/out of the money
+    x = inputs.uniform_box(200000, seed=31).astype(np.float32)
+    corners = np.array([[5, 100, 0.25, 0.02, 0.1], [30, 1, 10, 0.02, 0.5], [5, 100, 10, 0.02, 0.5],
+                        [30, 1, 0.25, 0.02, 0.1], [20, 20, 1, 0.02, 0.3]], np.float32).T
+    x = np.concatenate([x, corners], axis=1)
+    y, _, _ = run("exact", to_dev(x), 2, 4)
+    ref, scale = exact_ref(x)
+    check_outputs(y, ref, scale, what="exact box")
+
+
+@pytest.mark.parametrize("block", [64, 128, 192, 256])
+def test_exact_block_sizes(block):
+    x = inputs.portfolio(10007, 1024)
+    y, _, _ = run("exact", to_dev(x), 2, 5, block_size=block)
+    ref, scale = exact_ref(x)
+    check_outputs(y, ref, scale, what="exact block %d" % block)
+
+
+# -------------------------------------------------------------------- iACT
+
+IACT_CASES = [
+    # name, input builder, ipt, table, theta, tables/wave, level
+    ("config0", lambda: inputs.portfolio(65536, 1024), 16, 8, 0.05, 1, "wave"),
+    ("periodic8", lambda: inputs.periodic(65536, 8, jitter=1e-4), 16, 8, 0.05, 1, "wave"),
+    ("periodic2", lambda: inputs.periodic(65536, 2, jitter=1e-3), 16, 8, 0.05, 1, "wave"),
+    ("periodic8_mixed", lambda: inputs.periodic(65536, 8, jitter=1e-3), 16, 8, 0.08, 1, "wave"),
+    ("periodic16_t8", lambda: inputs.periodic(40000, 16, jitter=1e-4), 12, 8, 0.05, 1, "wave"),
+    ("ragged", lambda: inputs.periodic(4099, 4, jitter=1e-4), 3, 4, 0.05, 1, "wave"),
+    ("grouped", lambda: inputs.grouped(65536, 64, jitter=1e-4), 16, 4, 0.05, 1, "wave"),
+    ("thread_tpw64", lambda: inputs.periodic(65536, 8, jitter=1e-4), 16, 2, 0.05, 64, "thread"),
+    ("thread_tpw1", lambda: inputs.periodic(30000, 8, jitter=1e-3), 8, 8, 0.1, 1, "thread"),
+    ("wave_tpw4", lambda: inputs.periodic(65536, 8, jitter=1e-4), 16, 4, 0.05, 4, "wave"),
+    ("block_tpw2", lambda: inputs.periodic(65536, 8, jitter=1e-3), 16, 8, 0.08, 2, "block"),
+    ("table32", lambda: inputs.periodic(65536, 32, jitter=1e-4), 64, 32, 0.05, 1, "wave"),
+    ("table1", lambda: inputs.constant(5000), 7, 1, 0.05, 1, "wave"),
+]
+
+
+@pytest.mark.parametrize("case", IACT_CASES, ids=[c[0] for c in IACT_CASES])
+def test_iact_matches_oracle(case):
+    name, mk, ipt, t, theta, tpw, level = case
+    block = 256
+    say("iact", name)
+    x = mk()
+    n = x.shape[1]
+    y, tr, cnt = run("iact", to_dev(x), 2, ipt, table_size=t, threshold=theta, tables_per_wave=tpw, level=level)
+    yv, sv = oracle.region_values_f32out(x)
+    ora = oracle.iact(x, yv, sv, ipt, t, theta, tables_per_wave=tpw, group=group_of(level, block),
+                      out_init=np.full_like(yv, SENTINEL))
+    gdec, f = trace_dec(tr)
+    assert np.array_equal(gdec, ora["dec"]), "decision masks differ"
+    act = f["active"]
+    assert np.array_equal(f["votes"][act], ora["votes"][act])
+    assert np.array_equal(f["napprox"][act], ora["napprox"][act])
+    ow = ora["writer"]
+    assert np.array_equal(f["writer_valid"] & act, (ow >= 0) & act)
+    v = f["writer_valid"] & act
+    assert np.array_equal(f["writer"][v], ow[v])
+    check_outputs(y, ora["out"], ora["scale"], what="iact " + name)
+    ref, _ = exact_ref(x)
+    mg, mo = mape_pair(ref, y, ora["out"])
+    assert abs(mg - mo) <= 1e-4
+    assert cnt[0] == n and cnt[1] == int(ora["napprox"][act].sum())
+    say("  approx lanes %.4f  mape gpu %.3g oracle %.3g" % (cnt[1] / n, mg, mo))
+
+
+# --------------------------------------------------------------------- TAF
+
+TAF_CASES = [
+    # name, input builder, ipt, h, p, theta, level
+    ("config0", lambda: inputs.portfolio(65536, 1024), 16, 4, 4, 0.01, "wave"),
+    ("periodic8", lambda: inputs.periodic(65536, 8, jitter=1e-4), 16, 4, 4, 0.01, "wave"),
+    ("periodic8_mixed", lambda: inputs.periodic(65536, 8, jitter=1e-3), 16, 4, 4, 0.007, "wave"),
+    ("h2_p7", lambda: inputs.periodic(65536, 16, jitter=3e-4), 32, 2, 7, 0.005, "wave"),
+    ("h8", lambda: inputs.periodic(65536, 16, jitter=1e-4), 32, 8, 3, 0.01, "wave"),
+    ("ragged", lambda: inputs.periodic(4099, 4, jitter=1e-4), 5, 2, 2, 0.01, "wave"),
+    ("thread", lambda: inputs.periodic(65536, 8, jitter=1e-3), 16, 3, 2, 0.003, "thread"),
+    ("block", lambda: inputs.periodic(65536, 8, jitter=1e-3), 16, 3, 2, 0.006, "block"),
+    ("h1", lambda: inputs.constant(6000), 9, 1, 2, 0.01, "wave"),
+    ("mixed_h3", lambda: inputs.periodic(65536, 8, jitter=1e-3), 16, 3, 3, 0.006, "wave"),
+]
+
+
+def taf_band(theta):
+    """Relative band around the threshold inside which the GPU's FP32
+    region outputs (a few ulp from the FP64 values) may move a lane's RSD
+    across it: |dRSD| <~ 2 eps (1 + RSD) with eps <= 2e-6."""
+    return 1e-5 + 4e-6 * (1.0 + theta) / theta
+
+
+@pytest.mark.parametrize("case", TAF_CASES, ids=[c[0] for c in TAF_CASES])
+def test_taf_matches_oracle(case):
+    name, mk, ipt, h, p, theta, level = case
+    say("taf", name)
+    x = mk()
+    n = x.shape[1]
+    y, tr, cnt = run("taf", to_dev(x), 2, ipt, history_size=h, prediction_size=p, rsd_threshold=theta, level=level)
+    yv, sv = oracle.region_values_f32out(x)
+    ora = oracle.taf(yv, sv, ipt, h, p, theta, band=taf_band(theta), group=group_of(level, 256),
+                     out_init=np.full_like(yv, SENTINEL))
+    gdec, f = trace_dec(tr)
+    agree, compared, explained, cascaded = compare_decisions(gdec, ora["dec"], ipt, ora["fragile"])
+    assert agree >= 0.9999 * compared
+    say("  decisions agree %d/%d, explained %d, cascaded %d, fragile steps %d"
+        % (agree, compared, explained, cascaded, int(ora["fragile"].sum())))
+    # outputs on every wave whose history matched the oracle's
+    g = gdec.reshape(-1, ipt)
+    o = ora["dec"].reshape(-1, ipt)
+    same_wave = np.all(g == o, axis=1)
+    L = oracle.num_lanes(n, ipt)
+    item_wave = ((np.arange(n) % L) // 64)
+    mask = same_wave[item_wave]
+    check_outputs(y, ora["out"], ora["scale"], mask=mask, what="taf " + name)
+    ref, _ = exact_ref(x)
+    mg, mo = mape_pair(ref, y, ora["out"])
+    assert abs(mg - mo) <= 1e-4
+    assert cnt[0] == n
+    say("  approx lanes %.4f  mape gpu %.3g oracle %.3g" % (cnt[1] / n, mg, mo))
+
+
+# ------------------------------------------------------------- perforation
+
+PERFO_CASES = [
+    ("small10", "small", 10, 0, 20, 65536),
+    ("small10_ipt16", "small", 10, 0, 16, 65536),
+    ("small5", "small", 5, 0, 20, 65536),
+    ("small2", "small", 2, 0, 20, 65536),
+    ("small4_offset", "small", 4, 3, 9, 4099),
+    ("large4", "large", 4, 0, 8, 65536),
+    ("ini30", "ini", 30, 0, 4, 10007),
+    ("fini25", "fini", 25, 0, 4, 10007),
+]
+
+
+@pytest.mark.parametrize("case", PERFO_CASES, ids=[c[0] for c in PERFO_CASES])
+def test_perfo_matches_oracle(case):
+    name, kind, param, offset, ipt, n = case
+    say("perfo", name)
+    x = inputs.portfolio(n, 1024)
+    y, tr, cnt = run("perfo", to_dev(x), 2, ipt, kind=kind, param=param, offset=offset)
+    yv, sv = oracle.region_values_f32out(x)
+    k = {"small": 0, "large": 1, "ini": 2, "fini": 3}[kind]
+    ora = oracle.perfo(yv, sv, ipt, k, param, offset, out_init=np.full_like(yv, SENTINEL))
+    gdec, f = trace_dec(tr)
+    assert np.array_equal(gdec, ora["dec"])
+    skipped = ora["out"][0] == SENTINEL
+    assert np.all(y[:, skipped] == SENTINEL), "dropped items must keep their previous contents"
+    check_outputs(y, ora["out"], ora["scale"], mask=~skipped, what="perfo " + name)
+    assert cnt[0] == n and cnt[1] == int(skipped.sum())
+
+
+# --------------------------------------------------------------- collapse
+
+@pytest.mark.parametrize("level", ["thread", "wave", "block"])
+@pytest.mark.parametrize("ipt", [1, 7, 16])
+def test_zero_threshold_reproduces_exact_bitwise(level, ipt):
+    x = to_dev(inputs.periodic(20011, 8, jitter=1e-5))
+    ye, _, _ = run("exact", x, 2, ipt)
+    yi, ti, _ = run("iact", x, 2, ipt, table_size=8, threshold=0.0, level=level)
+    yt, tt, _ = run("taf", x, 2, ipt, history_size=2, prediction_size=4, rsd_threshold=0.0, level=level)
+    yp, tp, _ = run("perfo", x, 2, ipt, kind="small", param=0)
+    for yy, tt_ in ((yi, ti), (yt, tt), (yp, tp)):
+        assert np.array_equal(yy, ye)
+        assert not hpac.trace_fields(tt_)["approx"].any()
+    # the same inputs do approximate once the threshold is positive
+    if ipt >= 7:
+        _, t2, c2 = run("taf", x, 2, ipt, history_size=2, prediction_size=4, rsd_threshold=0.01, level=level)
+        assert c2[1] > 0
+
+
+def test_accurate_path_is_bitwise_exact_path():
+    # where a technique computes, it writes exactly hpac_exact's value
+    x = to_dev(inputs.periodic(65536, 8, jitter=1e-3))
+    ye, _, _ = run("exact", x, 2, 16)
+    yt, tr, _ = run("taf", x, 2, 16, history_size=4, prediction_size=4, rsd_threshold=0.007)
+    f = hpac.trace_fields(tr)
+    L = hpac.hpac_num_lanes(65536, 16)
+    i = np.arange(65536)
+    step = i // L
+    wave = (i % L) // 64
+    computed = ~f["approx"].reshape(-1, 16)[wave, step]
+    assert computed.any() and (~computed).any()
+    assert np.array_equal(yt[:, computed], ye[:, computed])
+
+
+# ------------------------------------------------------------ determinism
+
+def test_repeated_launches_are_bitwise_identical():
+    x = to_dev(inputs.periodic(65536, 8, jitter=1e-3))
+    runs = [run("iact", x, 2, 16, table_size=8, threshold=0.08) for _ in range(5)]
+    runs += [run("taf", x, 2, 16, history_size=4, prediction_size=4, rsd_threshold=0.007) for _ in range(5)]
+    for a, b in zip(runs[:4], runs[1:5]):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    for a, b in zip(runs[5:9], runs[6:10]):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+# --------------------------------------------------- full size (2^24 items)
+
+def test_full_size_config_against_oracle():
+    """2^24 options sorted by spot (pool 65,536): exact and each technique
+    at the launch configuration the benchmark times, against the oracle."""
+    n = 1 << 24
+    say("full-size inputs")
+    x = inputs.portfolio(n, 65536, sort_by_spot=True)
+    xd = to_dev(x)
+    ref, scale = exact_ref(x)
+    ye, _, c = run("exact", xd, 2, 1, trace=False)
+    check_outputs(ye, ref, scale, what="exact 2^24")
+    del ye
+    yv, sv = oracle.region_values_f32out(x)
+    say("full-size iact")
+    yi, ti, _ = run("iact", xd, 2, 16, table_size=8, threshold=0.05)
+    ora = oracle.iact(x, yv, sv, 16, 8, 0.05)
+    assert np.array_equal(trace_dec(ti)[0], ora["dec"])
+    check_outputs(yi, ora["out"], ora["scale"], what="iact 2^24")
+    del yi, ora
+    say("full-size taf")
+    yt, tt, _ = run("taf", xd, 2, 16, history_size=4, prediction_size=4, rsd_threshold=0.01)
+    ora = oracle.taf(yv, sv, 16, 4, 4, 0.01, band=taf_band(0.01))
+    compare_decisions(trace_dec(tt)[0], ora["dec"], 16, ora["fragile"])
+    mg, mo = mape_pair(ref, yt, ora["out"])
+    assert abs(mg - mo) <= 1e-4
+    del yt, ora
+    say("full-size perfo")
+    yp, tp, _ = run("perfo", xd, 2, 20, kind="small", param=10, fill=0.0)
+    ora = oracle.perfo(yv, sv, 20, 0, 10, 0)
+    skipped = ora["out"][0] == 0
+    check_outputs(yp, ora["out"], ora["scale"], mask=~skipped, what="perfo 2^24")
+    assert np.all(yp[:, skipped] == 0)
