@@ -47,7 +47,30 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-structured", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=1 << 24)
+    p.add_argument("--pmc-probe", action="store_true",
+                   help="only launch each kernel of the step three times plus a 256 MiB copy probe, untimed, "
+                        "for hardware-counter runs")
     return p.parse_args()
+
+
+COPY_PROBE_BYTES = 256 << 20
+
+
+def pmc_probe(torch, hpac, x_copies, n):
+    """Launches for a counter run: each technique 3 times on rotating inputs,
+    then the plain copy kernel 3 times over COPY_PROBE_BYTES (its counter
+    readings calibrate the byte counters)."""
+    dev = x_copies[0][0].device
+    outs = [torch.zeros(n, dtype=torch.float32, device=dev) for _ in range(2)]
+    for r in range(3):
+        for t in TECHS:
+            launch(hpac, t, x_copies[r % len(x_copies)], outs)
+    src = torch.zeros(COPY_PROBE_BYTES // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for r in range(3):
+        hpac.hpac_probe_copy(src, dst, COPY_PROBE_BYTES)
+    torch.cuda.synchronize()
+    print(json.dumps({"pmc_probe": "done", "n": n, "copy_bytes": COPY_PROBE_BYTES}), flush=True)
 
 
 def launch(hpac, name, x, outs, block=256, **extra):
@@ -194,6 +217,9 @@ def main():
             xd = [col.clone() for col in xd]
         x_copies.append(xd)
     torch.cuda.synchronize()
+    if args.pmc_probe:
+        pmc_probe(torch, hpac, x_copies, n)
+        return
     print("[bench] timing %d steps after %d warmup" % (args.steps, args.warmup), file=sys.stderr, flush=True)
     res = run_workload(torch, hpac, x_copies, n, args.steps, args.warmup)
     tech = summarize(res, n)

@@ -52,7 +52,9 @@ __device__ __forceinline__ uint32_t trace_word(int votes, int napprox, int write
   return t;
 }
 
-// Per-wave tallies, wave-uniform, flushed once per wave at kernel end.
+// Per-wave tallies (wave-uniform).  At kernel end each wave adds them into
+// the block's LDS sums and one thread adds those into the caller's counters,
+// so a launch issues at most 4 global atomics per workgroup.
 struct WaveStats {
   uint64_t lane_steps = 0, approx_lanes = 0, approx_wsteps = 0, wsteps = 0;
   __device__ __forceinline__ void add(int active, int napprox, bool wave_approx) {
@@ -61,13 +63,28 @@ struct WaveStats {
     approx_wsteps += wave_approx ? 1 : 0;
     wsteps += 1;
   }
-  __device__ __forceinline__ void flush(unsigned long long *c) const {
-    if (c && lane_id() == 0 && wsteps) {
-      atomicAdd(&c[0], (unsigned long long)lane_steps);
-      atomicAdd(&c[1], (unsigned long long)approx_lanes);
-      atomicAdd(&c[2], (unsigned long long)approx_wsteps);
-      atomicAdd(&c[3], (unsigned long long)wsteps);
+};
+
+// Every thread of the block calls begin() and end() (no early returns in the
+// kernels), and both are no-ops unless counters were requested.
+struct StatsSink {
+  unsigned long long *g;  // caller's counters or nullptr
+  unsigned long long *s;  // 4 sums in LDS
+  __device__ __forceinline__ void begin() {
+    if (!g) return;
+    if (threadIdx.x < 4) s[threadIdx.x] = 0;
+    __syncthreads();
+  }
+  __device__ __forceinline__ void end(const WaveStats &st) {
+    if (!g) return;
+    if (lane_id() == 0 && st.wsteps) {
+      atomicAdd(&s[0], (unsigned long long)st.lane_steps);
+      atomicAdd(&s[1], (unsigned long long)st.approx_lanes);
+      atomicAdd(&s[2], (unsigned long long)st.approx_wsteps);
+      atomicAdd(&s[3], (unsigned long long)st.wsteps);
     }
+    __syncthreads();
+    if (threadIdx.x < 4 && s[threadIdx.x]) atomicAdd(&g[threadIdx.x], s[threadIdx.x]);
   }
 };
 
@@ -82,7 +99,7 @@ struct BlockTally {
     if (threadIdx.x < 6) t[threadIdx.x] = 0;
     __syncthreads();
   }
-  __device__ __forceinline__ bool decide(int k, int wave_votes, int wave_active, bool *any_active) {
+  __device__ __forceinline__ bool decide(int k, int wave_votes, int wave_active) {
     int *cur = t + 2 * (k % 3);
     if (threadIdx.x == 0) {
       int *nxt = t + 2 * ((k + 1) % 3);
@@ -94,61 +111,130 @@ struct BlockTally {
       atomicAdd(&cur[1], wave_active);
     }
     __syncthreads();
-    const int votes = cur[0], act = cur[1];
-    *any_active = act > 0;
-    return majority(votes, act);
+    return majority(cur[0], cur[1]);
   }
 };
+
+// Geometry of one lane in the grid-stride loop.
+struct LaneGeom {
+  int64_t l;      // logical lane
+  int64_t wbase;  // first lane of the wave
+  int64_t bbase;  // first lane of the block
+  __device__ __forceinline__ LaneGeom() {
+    bbase = (int64_t)blockIdx.x * blockDim.x;
+    l = bbase + threadIdx.x;
+    wbase = l - lane_id();
+  }
+  // the wave (or block) has an active lane at step k
+  __device__ __forceinline__ bool wave_has(const KArgs &a, int k) const {
+    return wbase < a.L && wbase + (int64_t)k * a.L < a.n;
+  }
+  __device__ __forceinline__ bool block_has(const KArgs &a, int k) const { return bbase + (int64_t)k * a.L < a.n; }
+  __device__ __forceinline__ bool active(const KArgs &a, int k) const {
+    return l < a.L && l + (int64_t)k * a.L < a.n;
+  }
+  __device__ __forceinline__ int64_t item(const KArgs &a, int k) const { return l + (int64_t)k * a.L; }
+  __device__ __forceinline__ int64_t trace_index(const KArgs &a, int k) const { return (wbase >> 6) * a.ipt + k; }
+};
+
+// Inputs of the next step are loaded while the current step computes
+// (software pipelining).  The loads are issued unconditionally so that the
+// compiler can count them exactly and wait only for the ones it needs: a lane
+// that does not need step k's inputs loads the wave's first item of step
+// k-1 instead, a line the wave has just fetched, which costs no HBM traffic.
+template <class R>
+__device__ __forceinline__ void prefetch(const KArgs &a, const LaneGeom &g, int k, bool want, float (&xn)[R::kIn]) {
+  int64_t i = g.item(a, k);
+  if (!(want && k < a.ipt && g.active(a, k))) {
+    i = g.wbase + (int64_t)(k - 1) * a.L;
+    if (i >= a.n) i = a.n - 1;
+  }
+  load_inputs<R>(a, i, xn);
+}
+
+// Inputs of the first step (before the loop; conditional).
+template <class R>
+__device__ __forceinline__ void load_first(const KArgs &a, const LaneGeom &g, bool want, float (&x)[R::kIn]) {
+  if (want && g.active(a, 0)) load_inputs<R>(a, g.item(a, 0), x);
+}
+
+// Runs step(k, x_k, x_{k+1}) for k = 0, 1, ... while it returns true.
+template <int N, class Step>
+__device__ __forceinline__ void step_loop(int ipt, float (&xa)[N], float (&xb)[N], Step step) {
+  for (int k = 0; k < ipt; k += 2) {
+    if (!step(k, xa, xb)) break;
+    if (k + 1 >= ipt || !step(k + 1, xb, xa)) break;
+  }
+}
 
 // --------------------------------------------------------------- exact path
 
 template <class R, bool kStats>
 __global__ void __launch_bounds__(256) k_exact(KArgs a) {
-  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t wbase = l - lane_id();
-  if (wbase >= a.L) return;
+  __shared__ unsigned long long sums[4];
+  const LaneGeom g;
+  StatsSink sink{kStats ? a.counters : nullptr, sums};
+  sink.begin();
   WaveStats st;
-  for (int k = 0; k < a.ipt; ++k) {
-    const int64_t i = l + (int64_t)k * a.L;
-    if (wbase + (int64_t)k * a.L >= a.n) break;
-    const bool active = i < a.n;
+  float xa[R::kIn], xb[R::kIn];
+  load_first<R>(a, g, true, xa);
+  step_loop(a.ipt, xa, xb, [&](int k, float (&x)[R::kIn], float (&xn)[R::kIn]) {
+    if (!g.wave_has(a, k)) return false;
+    const bool active = g.active(a, k);
+    prefetch<R>(a, g, k + 1, true, xn);
     if (active) {
-      float x[R::kIn], y[R::kOut];
-      load_inputs<R>(a, i, x);
+      float y[R::kOut];
       R::eval(x, y);
-      store_outputs<R>(a, i, y);
+      store_outputs<R>(a, g.item(a, k), y);
     }
     if (kStats) {
-      const int nact = popc(ballot(active));
-      st.add(nact, 0, false);
-      if (a.trace && lane_id() == 0) a.trace[(wbase >> 6) * a.ipt + k] = trace_word(0, 0, -1, false, false);
+      st.add(popc(ballot(active)), 0, false);
+      if (a.trace && lane_id() == 0) a.trace[g.trace_index(a, k)] = trace_word(0, 0, -1, false, false);
     }
-  }
-  if (kStats) st.flush(a.counters);
+    return true;
+  });
+  sink.end(st);
 }
 
 // ---------------------------------------------------------------- perforation
 
+struct PerfoRule {
+  int kind, param, offset;
+  int64_t cut;
+  // herded: the step rule is identical for every lane
+  __device__ __forceinline__ bool step_skipped(int64_t k) const {
+    const int64_t kk = k + offset;
+    if (kind == kSmall) return param > 0 && (kk % param) == param - 1;
+    if (kind == kLarge) return param > 0 && (kk % param) != 0;
+    return false;
+  }
+  __device__ __forceinline__ bool skipped(int64_t k, int64_t i, int64_t n) const {
+    if (kind == kIni) return i < cut;
+    if (kind == kFini) return i >= n - cut;
+    return step_skipped(k);
+  }
+};
+
+// Perforation with the per-(wave, step) trace and counters.
 template <class R>
 __global__ void __launch_bounds__(256) k_perfo(KArgs a, int kind, int param, int offset) {
-  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t wbase = l - lane_id();
-  if (wbase >= a.L) return;
-  const int64_t cut = (kind == kIni || kind == kFini) ? ((int64_t)param * a.n) / 100 : 0;
+  __shared__ unsigned long long sums[4];
+  const LaneGeom g;
+  StatsSink sink{a.counters, sums};
+  sink.begin();
+  const PerfoRule rule{kind, param, offset, (kind == kIni || kind == kFini) ? ((int64_t)param * a.n) / 100 : 0};
   WaveStats st;
-  for (int k = 0; k < a.ipt; ++k) {
-    const int64_t i = l + (int64_t)k * a.L;
-    if (wbase + (int64_t)k * a.L >= a.n) break;
-    const bool active = i < a.n;
-    const int64_t kk = (int64_t)k + offset;
-    bool skip = false;  // herded: identical for every lane at step k
-    if (kind == kSmall) skip = param > 0 && (kk % param) == param - 1;
-    if (kind == kLarge) skip = param > 0 && (kk % param) != 0;
-    if (kind == kIni) skip = i < cut;
-    if (kind == kFini) skip = i >= a.n - cut;
+  float xa[R::kIn], xb[R::kIn];
+  load_first<R>(a, g, !rule.skipped(0, g.item(a, 0), a.n), xa);
+  step_loop(a.ipt, xa, xb, [&](int k, float (&x)[R::kIn], float (&xn)[R::kIn]) {
+    if (!g.wave_has(a, k)) return false;
+    const int64_t i = g.item(a, k);
+    const bool active = g.active(a, k);
+    const bool skip = rule.skipped(k, i, a.n);
+    // the next executed step's inputs; dropped steps load nothing
+    prefetch<R>(a, g, k + 1, !rule.skipped(k + 1, g.item(a, k + 1), a.n), xn);
     if (active && !skip) {
-      float x[R::kIn], y[R::kOut];
-      load_inputs<R>(a, i, x);
+      float y[R::kOut];
       R::eval(x, y);
       store_outputs<R>(a, i, y);
     }
@@ -156,11 +242,37 @@ __global__ void __launch_bounds__(256) k_perfo(KArgs a, int kind, int param, int
       const int nact = popc(ballot(active));
       const int nskip = popc(ballot(active && skip));
       st.add(nact, nskip, nskip > 0);
-      if (a.trace && lane_id() == 0)
-        a.trace[(wbase >> 6) * a.ipt + k] = trace_word(0, nskip, -1, nskip > 0, false);
+      if (a.trace && lane_id() == 0) a.trace[g.trace_index(a, k)] = trace_word(0, nskip, -1, nskip > 0, false);
     }
+    return true;
+  });
+  sink.end(st);
+}
+
+// Perforation without trace or counters.  The region keeps no state, so the
+// items a herded pattern keeps -- whole grid-stride steps, i.e. the item
+// ranges [kL, (k+1)L) of the kept steps k -- can be evaluated by any lanes:
+// one item per lane, workgroups mapped onto the kept ranges, dropped ranges
+// never launched.  The outputs are those of k_perfo bit for bit.
+template <class R>
+__global__ void __launch_bounds__(256) k_perfo_dense(KArgs a, int blocks_per_step, int M, int kept_per_period,
+                                                     int special, int large) {
+  // block -> j-th kept step.  Kept steps repeat with period M: SMALL keeps
+  // every position of a period but `special`, LARGE keeps only `special`.
+  const int b = blockIdx.x;
+  const int j = b / blocks_per_step;
+  const int P = j / kept_per_period;
+  const int r = j - P * kept_per_period;
+  const int s = large ? special : (r < special ? r : r + 1);
+  const int64_t k = (int64_t)P * M + s;
+  const int64_t i = k * a.L + (int64_t)(b - j * blocks_per_step) * blockDim.x + threadIdx.x;
+  const int64_t end = (k + 1) * a.L < a.n ? (k + 1) * a.L : a.n;
+  if (i < end) {
+    float x[R::kIn], y[R::kOut];
+    load_inputs<R>(a, i, x);
+    R::eval(x, y);
+    store_outputs<R>(a, i, y);
   }
-  st.flush(a.counters);
 }
 
 // ------------------------------------------------------------------- iACT
@@ -187,16 +299,16 @@ template <class R, int LEVEL>
 __global__ void __launch_bounds__(256) k_iact(KArgs a, int tsize, float theta, int tpw) {
   extern __shared__ float lds[];
   __shared__ int tally_mem[6];
+  __shared__ unsigned long long sums[4];
   constexpr int E = entry_floats<R>();
+  const LaneGeom g;
   const int lane = lane_id();
   const int wib = threadIdx.x >> 6;
   const int lpt = kWave / tpw;  // lanes per table
   const int tab_in_wave = lane / lpt;
   float *tab = lds + ((size_t)wib * tpw + tab_in_wave) * tsize * E;
-  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t wbase = l - lane;
-  const int64_t bbase = (int64_t)blockIdx.x * blockDim.x;
-  if (LEVEL != kBlock && wbase >= a.L) return;
+  StatsSink sink{a.counters, sums};
+  sink.begin();
   BlockTally tally{tally_mem};
   if (LEVEL == kBlock) tally.init();
   const float thr2 = theta * theta;
@@ -204,44 +316,35 @@ __global__ void __launch_bounds__(256) k_iact(KArgs a, int tsize, float theta, i
   const uint64_t segmask = lpt == kWave ? ~0ull : (((1ull << lpt) - 1) << seg0);
   int cnt = 0, ins = 0;  // valid entries and insertions of this lane's table
   WaveStats st;
+  float xa[R::kIn], xb[R::kIn];
+  load_first<R>(a, g, true, xa);
 
-  for (int k = 0; k < a.ipt; ++k) {
-    const int64_t step0 = (int64_t)k * a.L;
-    if (LEVEL != kBlock && wbase + step0 >= a.n) break;
-    if (LEVEL == kBlock && bbase + step0 >= a.n) break;
-    const int64_t i = l + step0;
-    const bool active = l < a.L && i < a.n;
-    // read phase: nearest valid entry of this lane's table
-    float x[R::kIn];
+  step_loop(a.ipt, xa, xb, [&](int k, float (&x)[R::kIn], float (&xn)[R::kIn]) {
+    if (LEVEL != kBlock && !g.wave_has(a, k)) return false;
+    if (LEVEL == kBlock && !g.block_has(a, k)) return false;
+    const int64_t i = g.item(a, k);
+    const bool active = g.active(a, k);
+    prefetch<R>(a, g, k + 1, true, xn);
+    // read phase: distance to the nearest valid entry of this lane's table
     float md2 = INFINITY;
-    int arg = -1;
-    if (active) {
-      load_inputs<R>(a, i, x);
-      for (int e = 0; e < cnt; ++e) {
-        const float d2 = dist2<R::kIn>(x, tab + e * E);
-        if (d2 < md2) {
-          md2 = d2;
-          arg = e;
-        }
-      }
-    }
-    const bool hit = active && arg >= 0 && md2 < thr2;
+    if (active)
+      for (int e = 0; e < cnt; ++e) md2 = fminf(md2, dist2<R::kIn>(x, tab + e * E));
+    const bool hit = active && cnt > 0 && md2 < thr2;
     const uint64_t amask = ballot(active);
     const uint64_t vmask = ballot(hit);
     bool group_approx;
-    bool wave_live = amask != 0;
-    if (LEVEL == kThread) {
-      group_approx = hit;
-    } else if (LEVEL == kWaveLvl) {
-      group_approx = majority(popc(vmask), popc(amask));
-    } else {
-      bool any;
-      group_approx = tally.decide(k, popc(vmask), popc(amask), &any);
-    }
-    const bool lane_approx = active && group_approx && arg >= 0;
+    if (LEVEL == kThread) group_approx = hit;
+    else if (LEVEL == kWaveLvl) group_approx = majority(popc(vmask), popc(amask));
+    else group_approx = tally.decide(k, popc(vmask), popc(amask));
+    const bool lane_approx = active && group_approx && cnt > 0;
     const bool computes = active && !lane_approx;
     float y[R::kOut];
     if (lane_approx) {
+      // the nearest entry: lowest slot at the minimum distance (recomputing
+      // the identical FP32 distances)
+      int arg = 0;
+      for (int e = cnt - 1; e >= 0; --e)
+        if (dist2<R::kIn>(x, tab + e * E) == md2) arg = e;
 #pragma unroll
       for (int o = 0; o < R::kOut; ++o) y[o] = tab[arg * E + R::kIn + o];
     }
@@ -270,38 +373,40 @@ __global__ void __launch_bounds__(256) k_iact(KArgs a, int tsize, float theta, i
       writer0 = cand0 ? lowest_lane(cand0) : -1;
       wave_lds_fence();
     }
-    if (wave_live && (a.trace || a.counters)) {
+    if (amask && (a.trace || a.counters)) {
       const int nact = popc(amask);
       const int napx = popc(ballot(lane_approx));
       const bool wave_approx = LEVEL == kThread ? napx > 0 : group_approx;
       st.add(nact, napx, wave_approx);
       if (a.trace && lane == 0)
-        a.trace[(wbase >> 6) * a.ipt + k] = trace_word(popc(vmask), napx, writer0, wave_approx, true);
+        a.trace[g.trace_index(a, k)] = trace_word(popc(vmask), napx, writer0, wave_approx, true);
     }
-  }
-  st.flush(a.counters);
+    return true;
+  });
+  sink.end(st);
 }
 
 // -------------------------------------------------------------------- TAF
 
-// RSD criterion of one lane, FP64, all outputs must pass.
+// RSD criterion of one lane in FP64 over every output o of the window:
+// with s = sum_q w_q and D = sum_q (h w_q - s)^2 (= h^3 var), the test
+// var < theta^2 mu^2 is D < h theta^2 s^2, and var == 0 is D == 0, which
+// passes whenever theta > 0.  No division is needed.
 template <int H, int NO>
-__device__ __forceinline__ bool rsd_below(const float (&w)[H][NO], double th, double th2) {
+__device__ __forceinline__ bool rsd_below(const float (&w)[H][NO], double th2, bool th_pos) {
   bool ok = true;
 #pragma unroll
   for (int o = 0; o < NO; ++o) {
     double s = 0.0;
 #pragma unroll
     for (int q = 0; q < H; ++q) s += (double)w[q][o];
-    const double mu = s / H;
-    double var = 0.0;
+    double D = 0.0;
 #pragma unroll
     for (int q = 0; q < H; ++q) {
-      const double d = (double)w[q][o] - mu;
-      var += d * d;
+      const double d = (double)H * (double)w[q][o] - s;
+      D = __builtin_fma(d, d, D);
     }
-    var /= H;
-    const bool v = var == 0.0 ? th > 0.0 : var < th2 * (mu * mu);
+    const bool v = D == 0.0 ? th_pos : D < (double)H * th2 * (s * s);
     ok = ok && v;
   }
   return ok;
@@ -310,11 +415,11 @@ __device__ __forceinline__ bool rsd_below(const float (&w)[H][NO], double th, do
 template <class R, int LEVEL, int H>
 __global__ void __launch_bounds__(256) k_taf(KArgs a, int psize, float theta) {
   __shared__ int tally_mem[6];
+  __shared__ unsigned long long sums[4];
+  const LaneGeom g;
   const int lane = lane_id();
-  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t wbase = l - lane;
-  const int64_t bbase = (int64_t)blockIdx.x * blockDim.x;
-  if (LEVEL != kBlock && wbase >= a.L) return;
+  StatsSink sink{a.counters, sums};
+  sink.begin();
   BlockTally tally{tally_mem};
   if (LEVEL == kBlock) tally.init();
   const double th = (double)theta;
@@ -327,24 +432,28 @@ __global__ void __launch_bounds__(256) k_taf(KArgs a, int psize, float theta) {
   int fill = 0;
   int rho = 0;  // remaining approximate steps (uniform per group)
   WaveStats st;
+  float xa[R::kIn], xb[R::kIn];
+  load_first<R>(a, g, true, xa);
 
-  for (int k = 0; k < a.ipt; ++k) {
-    const int64_t step0 = (int64_t)k * a.L;
-    if (LEVEL != kBlock && wbase + step0 >= a.n) break;
-    if (LEVEL == kBlock && bbase + step0 >= a.n) break;
-    const int64_t i = l + step0;
-    const bool active = l < a.L && i < a.n;
+  step_loop(a.ipt, xa, xb, [&](int k, float (&x)[R::kIn], float (&xn)[R::kIn]) {
+    if (LEVEL != kBlock && !g.wave_has(a, k)) return false;
+    if (LEVEL == kBlock && !g.block_has(a, k)) return false;
+    const int64_t i = g.item(a, k);
+    const bool active = g.active(a, k);
     const bool stable = rho > 0;
     const bool lane_approx = active && stable;
     const bool computes = active && !stable;
+    // Inputs of step k+1 are needed unless it is certainly approximate
+    // (this step is approximate with more to come).  After a passing vote the
+    // speculative load of step k+1 goes unused.
+    prefetch<R>(a, g, k + 1, !stable || rho == 1, xn);
     bool crit = false, voted = false;
     if (lane_approx) {
 #pragma unroll
       for (int o = 0; o < R::kOut; ++o) a.out[o][i] = win[H - 1][o];
     }
     if (computes) {
-      float x[R::kIn], y[R::kOut];
-      load_inputs<R>(a, i, x);
+      float y[R::kOut];
       R::eval(x, y);
       store_outputs<R>(a, i, y);
 #pragma unroll
@@ -356,40 +465,39 @@ __global__ void __launch_bounds__(256) k_taf(KArgs a, int psize, float theta) {
       fill = fill < H ? fill + 1 : H;
       if (fill == H) {
         voted = true;
-        crit = rsd_below<H, R::kOut>(win, th, th2);
+        crit = rsd_below<H, R::kOut>(win, th2, th > 0.0);
       }
     }
     const uint64_t amask = ballot(active);
     const uint64_t vmask = ballot(crit);
     const bool any_vote = ballot(voted) != 0;
     bool wave_approx;
+    bool pass = false;
     if (LEVEL == kThread) {
-      if (stable) rho -= 1;
-      else if (crit) rho = psize;
+      pass = crit;
       wave_approx = ballot(lane_approx) != 0;
     } else if (LEVEL == kWaveLvl) {
+      pass = any_vote && majority(popc(vmask), popc(amask));
       wave_approx = stable && amask != 0;
-      if (stable) rho -= 1;
-      else if (any_vote && majority(popc(vmask), popc(amask))) rho = psize;
     } else {
       // every wave of the block takes part in the tally at every step; the
       // result only matters after an accurate step whose windows were full
       // (before that no lane's criterion holds, so the majority fails)
-      bool any;
-      const bool pass = tally.decide(k, popc(vmask), popc(amask), &any);
+      pass = tally.decide(k, popc(vmask), popc(amask)) && !stable;
       wave_approx = stable && amask != 0;
-      if (stable) rho -= 1;
-      else if (pass) rho = psize;
     }
+    if (stable) rho -= 1;
+    else if (pass) rho = psize;
     if (amask && (a.trace || a.counters)) {
       const int nact = popc(amask);
       const int napx = popc(ballot(lane_approx));
       st.add(nact, napx, wave_approx);
       if (a.trace && lane == 0)
-        a.trace[(wbase >> 6) * a.ipt + k] = trace_word(any_vote ? popc(vmask) : 0, napx, -1, wave_approx, any_vote);
+        a.trace[g.trace_index(a, k)] = trace_word(any_vote ? popc(vmask) : 0, napx, -1, wave_approx, any_vote);
     }
-  }
-  st.flush(a.counters);
+    return true;
+  });
+  sink.end(st);
 }
 
 // ------------------------------------------------------------------ probe
@@ -423,7 +531,42 @@ hipError_t launch_exact(const LaunchCfg &c, const KArgs &a) {
 
 template <class R>
 static hipError_t perfo_r(const LaunchCfg &c, const KArgs &a, int kind, int param, int offset) {
-  hipLaunchKernelGGL((k_perfo<R>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a, kind, param, offset);
+  // the dense paths launch up to ceil(n / block) workgroups
+  if (a.trace || a.counters || param == 0 || (a.n + c.block - 1) / c.block + a.ipt > 2147483647) {
+    hipLaunchKernelGGL((k_perfo<R>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a, kind, param, offset);
+    return hipGetLastError();
+  }
+  if (kind == kIni || kind == kFini) {
+    // a contiguous kept range: the exact kernel over it, one item per lane
+    const int64_t cut = ((int64_t)param * a.n) / 100;
+    KArgs b = a;
+    const int64_t lo = kind == kIni ? cut : 0;
+    b.n = a.n - cut;
+    b.ipt = 1;
+    b.L = ((b.n + 63) / 64) * 64;
+    for (int j = 0; j < R::kIn; ++j) b.in[j] = a.in[j] + lo;
+    for (int o = 0; o < R::kOut; ++o) b.out[o] = a.out[o] + lo;
+    if (b.n == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_exact<R, false>), grid_for(b, c.block), dim3(c.block), 0, c.stream, b);
+    return hipGetLastError();
+  }
+  // SMALL / LARGE: kept steps repeat with period M
+  const int M = param;
+  const int off = (int)(offset % M);
+  const int special = kind == kSmall ? ((M - 1 - off) % M + M) % M : ((M - off) % M + M) % M;
+  const int kept_per_period = kind == kSmall ? M - 1 : 1;
+  if (kept_per_period == 0) return hipSuccess;  // SMALL with M = 1 drops every step
+  const int64_t steps = (a.n + a.L - 1) / a.L;  // steps that hold items
+  // kept steps below `steps`
+  int64_t kept = (steps / M) * kept_per_period;
+  for (int64_t st = (steps / M) * M; st < steps; ++st) {
+    const int pos = (int)(st % M);
+    kept += kind == kSmall ? pos != special : pos == special;
+  }
+  if (kept == 0) return hipSuccess;
+  const int64_t bps = (a.L + c.block - 1) / c.block;
+  hipLaunchKernelGGL((k_perfo_dense<R>), dim3((unsigned)(kept * bps)), dim3(c.block), 0, c.stream, a, (int)bps, M,
+                     kept_per_period, special, kind == kLarge ? 1 : 0);
   return hipGetLastError();
 }
 

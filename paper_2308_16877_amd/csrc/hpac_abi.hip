@@ -34,6 +34,7 @@ bool region_shape(int region, RegionShape *s) {
 
 constexpr int64_t kMaxItems = (int64_t)1 << 40;
 constexpr int32_t kMaxIpt = 65536;
+constexpr int64_t kMaxBlocks = 2147483647;
 
 int64_t num_lanes(int64_t n, int32_t ipt) {
   const int64_t per = (n + ipt - 1) / ipt;
@@ -66,6 +67,9 @@ hpac_status check_io(const char *fn, const hpac_region_io *io, hpac::KArgs *a, h
       if ((uintptr_t)io->out[o] % 4) return fail(HPAC_EINVAL, "%s: output column %d is not 4-byte aligned", fn, o);
     }
   }
+  if ((num_lanes(io->n, io->items_per_lane) + block - 1) / block > kMaxBlocks)
+    return fail(HPAC_EINVAL, "%s: %lld items at %d items per lane need more than 2^31-1 workgroups; raise items_per_lane",
+                fn, (long long)io->n, io->items_per_lane);
   if ((uintptr_t)io->trace % 4) return fail(HPAC_EINVAL, "%s: trace is not 4-byte aligned", fn);
   if ((uintptr_t)io->counters % 8) return fail(HPAC_EINVAL, "%s: counters are not 8-byte aligned", fn);
   for (int j = 0; j < hpac::kMaxIn; ++j) a->in[j] = j < rs.n_in && io->n > 0 ? (const float *)io->in[j] : nullptr;

@@ -26,21 +26,21 @@ def outputs(n_out, n, fill=SENTINEL):
     return [torch.full((n,), fill, dtype=torch.float32, device=DEV) for _ in range(n_out)]
 
 
-def run(technique, x_dev, n_out, ipt, *, block_size=0, trace=True, fill=SENTINEL, **params):
+def run(technique, x_dev, n_out, ipt, *, block_size=0, trace=True, counters=True, fill=SENTINEL, **params):
     """Run one entry point; returns (outputs (n_out, n) float64 numpy,
-    trace words or None, counters)."""
+    trace words or None, counters or None)."""
     n = x_dev[0].numel()
     outs = outputs(n_out, n, fill)
     tr = None
     if trace:
         tr = torch.zeros(max(hpac.hpac_trace_entries(n, ipt), 1), dtype=torch.int32, device=DEV)
-    cnt = torch.zeros(hpac.NUM_COUNTERS, dtype=torch.int64, device=DEV)
+    cnt = torch.zeros(hpac.NUM_COUNTERS, dtype=torch.int64, device=DEV) if counters else None
     fn = {"exact": hpac.hpac_exact, "iact": hpac.hpac_iact, "taf": hpac.hpac_taf, "perfo": hpac.hpac_perfo}[technique]
     fn(x_dev, outs, items_per_lane=ipt, block_size=block_size, trace=tr, counters=cnt, **params)
     torch.cuda.synchronize()
     y = np.stack([o.cpu().numpy().astype(np.float64) for o in outs])
     t = tr.cpu().numpy().view(np.uint32) if tr is not None else None
-    return y, t, cnt.cpu().numpy()
+    return y, t, (cnt.cpu().numpy() if cnt is not None else None)
 
 
 def check_outputs(y_gpu, y_ref, scale, rel=1e-5, mask=None, what=""):
@@ -63,22 +63,23 @@ def trace_dec(t):
     return d, f
 
 
-def compare_decisions(gpu_dec, ora_dec, ipt, fragile=None):
+def compare_decisions(gpu_dec, ora_dec, ipt, fragile=None, lag=0):
     """Walk each wave's steps in order.  Returns (agree, compared, explained,
-    cascaded).  A disagreement is explained only where the oracle marked
-    the step fragile (a statistic within the tolerance band of its
-    threshold could flip the vote); the rest of that wave then follows a
+    cascaded).  A disagreement first seen at step k is explained only where
+    the oracle marked step k - lag fragile (a statistic within the band of
+    its threshold could flip the vote there; for TAF the vote at step k-1
+    decides step k, so lag = 1).  The rest of that wave then follows a
     different history and is not compared.  Any unexplained disagreement
     fails."""
     g = gpu_dec.reshape(-1, ipt)
     o = ora_dec.reshape(-1, ipt)
     fr = fragile.reshape(-1, ipt) if fragile is not None else np.zeros_like(o, dtype=np.uint8)
     neq = g != o
-    agree = compared = explained = cascaded = 0
+    explained = cascaded = 0
     bad = []
     for w in np.nonzero(neq.any(axis=1))[0]:
         k = int(np.argmax(neq[w]))
-        if fr[w, k]:
+        if k - lag >= 0 and fr[w, k - lag]:
             explained += 1
             cascaded += ipt - k - 1
         else:

@@ -61,6 +61,7 @@ def test_invalid_io_is_rejected_before_any_hip_call():
     expect(E, hpac.hpac_exact, **io(block_size=512))
     expect(E, hpac.hpac_exact, **io(n=-5))
     expect(E, hpac.hpac_exact, **io(n=2**40 + 1))
+    expect(E, hpac.hpac_exact, **io(n=2**40, items_per_lane=1))  # 2^32 workgroups
     expect(E, hpac.hpac_exact, **io(inputs=[FAKE] * 4))
     expect(E, hpac.hpac_exact, **io(outputs=[FAKE] * 3, region=0))
     expect(E, hpac.hpac_exact, **io(inputs=[FAKE, 0, FAKE, FAKE, FAKE]))
