@@ -296,7 +296,8 @@ __device__ __forceinline__ float dist2(const float (&x)[N], const float *e) {
 }
 
 template <class R, int LEVEL>
-__global__ void __launch_bounds__(256) k_iact(KArgs a, int tsize, float theta, int tpw) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k_iact(KArgs a, int tsize, float theta,
+                                                                                       int tpw) {
   extern __shared__ float lds[];
   __shared__ int tally_mem[6];
   __shared__ unsigned long long sums[4];

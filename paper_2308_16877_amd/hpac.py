@@ -156,6 +156,49 @@ def hpac_perfo(inputs, outputs, kind, param, offset=0, **kw):
     _call("hpac_perfo", lib().hpac_perfo(ctypes.byref(io), k, param, offset))
 
 
+class Prepared:
+    """A launch whose argument marshalling is done once: calling it issues
+    the same entry point with the same columns and parameters again on the
+    given stream (default: the stream chosen at preparation).  For timing
+    loops and serving loops where per-call Python work would dominate."""
+
+    _ENTRY = {"exact": "hpac_exact", "iact": "hpac_iact", "taf": "hpac_taf", "perfo": "hpac_perfo"}
+
+    def __init__(self, technique, inputs, outputs, params=(), **io_kw):
+        self.name = self._ENTRY[technique]
+        self.io = make_io(inputs, outputs, **io_kw)
+        self.fn = getattr(lib(), self.name)
+        self.args = (ctypes.byref(self.io),) + tuple(params)
+
+    def __call__(self, stream=None):
+        if stream is not None:
+            self.io.stream = stream if isinstance(stream, int) else stream.cuda_stream
+        st = self.fn(*self.args)
+        if st != HPAC_OK:
+            _call(self.name, st)
+
+
+def prepare(technique, inputs, outputs, **kw):
+    """Prepared launch of hpac_<technique>; keyword arguments as for the
+    function of that name."""
+    io_keys = ("n", "region", "items_per_lane", "block_size", "stream", "trace", "counters")
+    io_kw = {k: kw.pop(k) for k in list(kw) if k in io_keys}
+    if technique == "iact":
+        params = (kw.pop("table_size"), ctypes.c_float(kw.pop("threshold")), kw.pop("tables_per_wave", 1),
+                  _level(kw.pop("level", "wave")))
+    elif technique == "taf":
+        params = (kw.pop("history_size"), kw.pop("prediction_size"), ctypes.c_float(kw.pop("rsd_threshold")),
+                  _level(kw.pop("level", "wave")))
+    elif technique == "perfo":
+        k = kw.pop("kind")
+        params = (PERFO_KINDS[k] if isinstance(k, str) else int(k), kw.pop("param"), kw.pop("offset", 0))
+    else:
+        params = ()
+    if kw:
+        raise TypeError("unexpected arguments: %s" % sorted(kw))
+    return Prepared(technique, inputs, outputs, params, **io_kw)
+
+
 def hpac_probe_copy(src, dst, nbytes, stream=None):
     _call("hpac_probe_copy", lib().hpac_probe_copy(_addr(src), _addr(dst), nbytes, _stream(stream, [src, dst])))
 

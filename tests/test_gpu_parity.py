@@ -163,7 +163,14 @@ def test_taf_matches_oracle(case):
         gdec = np.where(f["active"], f["napprox"], -1)
         odec = np.where(ora["dec"] >= 0, ora["napprox"], -1)
     agree, compared, explained, cascaded = compare_decisions(gdec, odec, ipt, ora["fragile"], lag=1)
-    assert agree >= 0.9999 * compared
+    if level == "thread":
+        # lanes decide alone: the mask is per lane; count lane-steps that
+        # differ (at least |napprox_gpu - napprox_oracle| per wave-step)
+        act_lanes = int(np.where(ora["dec"] >= 0, 1, 0).sum()) * 64
+        diff = int(np.abs(np.where(gdec >= 0, gdec, 0) - np.where(odec >= 0, odec, 0)).sum())
+        assert diff <= 1e-4 * act_lanes + cascaded * 64
+    else:
+        assert agree >= 0.9999 * compared
     say("  decisions agree %d/%d, explained %d, cascaded %d, fragile steps %d"
         % (agree, compared, explained, cascaded, int(ora["fragile"].sum())))
     # outputs on every wave whose history matched the oracle's
