@@ -170,6 +170,95 @@ def summarize(res, n):
     return out
 
 
+def time_pairs(torch, legs, steps, warmup):
+    """Average HIP-event time (ms) of each named sequence of launches."""
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, fns in legs.items():
+        for _ in range(warmup):
+            for f in fns:
+                f()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            for f in fns:
+                f()
+        b.record(stream)
+        torch.cuda.synchronize()
+        out[name] = a.elapsed_time(b) / steps
+    return out
+
+
+def greeks_leg(torch, hpac, x_dev, n, steps):
+    """Call Greeks (upstream (1, 0)) for 2^24 options: exact forward + the
+    recomputing adjoint, against iACT (table 16, threshold 0.05) on the
+    price-and-Jacobian region + the saved-Jacobian VJP."""
+    dev = x_dev[0].device
+    f32 = dict(dtype=torch.float32, device=dev)
+    ones = torch.ones(n, **f32)
+    price = [torch.zeros(n, **f32) for _ in range(2)]
+    grads_exact = [torch.zeros(n, **f32) for _ in range(5)]
+    grads_iact = [torch.zeros(n, **f32) for _ in range(5)]
+    full = [torch.zeros(n, **f32) for _ in range(12)]
+    stream = torch.cuda.current_stream()
+    fwd_exact = hpac.prepare("exact", x_dev, price, items_per_lane=1, block_size=256, stream=stream)
+    fwd_iact = hpac.prepare("iact", x_dev, full, items_per_lane=16, block_size=256, stream=stream,
+                            region=hpac.REGION_BS_PRICE_GRAD, table_size=16, threshold=0.05)
+    legs = {
+        "exact_fwd_adjoint": [fwd_exact, lambda: hpac.hpac_bs_adjoint(x_dev, ones, None, grads_exact)],
+        "iact_fwd_vjp": [fwd_iact, lambda: hpac.hpac_bs_vjp(full[2:], ones, None, grads_iact)],
+    }
+    t = time_pairs(torch, legs, steps, 2)
+    cnt = torch.zeros(hpac.NUM_COUNTERS, dtype=torch.int64, device=dev)
+    hpac.hpac_iact(x_dev, full, 16, 0.05, items_per_lane=16, region=hpac.REGION_BS_PRICE_GRAD, counters=cnt)
+    hpac.hpac_bs_vjp(full[2:], ones, None, grads_iact)
+    torch.cuda.synchronize()
+    c = cnt.cpu().tolist()
+    return {"workload": "call Greeks (delta, dC/dK, theta, rho, vega) of the benchmark's 2^24 options",
+            "exact_fwd_adjoint_ms": t["exact_fwd_adjoint"], "iact_fwd_vjp_ms": t["iact_fwd_vjp"],
+            "exact_items_per_s": n / (t["exact_fwd_adjoint"] * 1e-3),
+            "iact_items_per_s": n / (t["iact_fwd_vjp"] * 1e-3),
+            "iact_speedup_vs_exact": t["exact_fwd_adjoint"] / t["iact_fwd_vjp"],
+            "iact_approx_frac": c[1] / max(c[0], 1),
+            "iact_gradient_mape_vs_exact": mape_torch(torch, grads_exact, grads_iact)}
+
+
+def precision_leg(torch, hpac, x_dev, n, steps):
+    """The exact region on the benchmark's 2^24 options with half-precision
+    columns (10 B in + 4 B out per item) and with the FP16 / BF16 bodies:
+    items/s and the error of each result against the FP32 exact kernel,
+    relative to max(|price|, tau)."""
+    stream = torch.cuda.current_stream()
+    ref = [torch.zeros(n, dtype=torch.float32, device=x_dev[0].device) for _ in range(2)]
+    hpac.hpac_exact(x_dev, ref, items_per_lane=1)
+    variants = {
+        "fp32_body_fp32_columns": (hpac.REGION_BS_PRICE, torch.float32),
+        "fp32_body_fp16_columns": (hpac.REGION_BS_PRICE, torch.float16),
+        "fp32_body_bf16_columns": (hpac.REGION_BS_PRICE, torch.bfloat16),
+        "fp16_body_fp16_columns": (hpac.REGION_BS_PRICE_F16, torch.float16),
+        "bf16_body_bf16_columns": (hpac.REGION_BS_PRICE_BF16, torch.bfloat16),
+        "fp16_body_fp32_columns": (hpac.REGION_BS_PRICE_F16, torch.float32),
+    }
+    legs, outs = {}, {}
+    for name, (region, dt) in variants.items():
+        xs = [c.to(dt) for c in x_dev]
+        o = [torch.zeros(n, dtype=dt, device=x_dev[0].device) for _ in range(2)]
+        outs[name] = o
+        legs[name] = [hpac.prepare("exact", xs, o, items_per_lane=1, block_size=256, stream=stream, region=region)]
+    t = time_pairs(torch, legs, steps, 2)
+    res = {}
+    for name in variants:
+        e = torch.stack(ref).double()
+        a = torch.stack([c.double() for c in outs[name]])
+        rel = (e - a).abs() / e.abs().clamp_min(MAPE_TAU)
+        res[name] = {"ms": t[name], "items_per_s": n / (t[name] * 1e-3),
+                     "speedup_vs_fp32": t["fp32_body_fp32_columns"] / t[name],
+                     "mape_vs_fp32": float(rel.mean()), "max_rel_err_vs_fp32": float(rel.max())}
+    return res
+
+
 def cpu_baseline(x, sample):
     """The oracle, untuned, on the first `sample` items of the workload: the
     same four legs as one GPU step (exact prices; iACT, TAF and perforation
@@ -254,6 +343,16 @@ def main():
                                                             "approx_frac")} for t, v in ts.items()}}
         del xs_copies
 
+    greeks = None
+    if not args.no_structured:
+        print("[bench] greeks", file=sys.stderr, flush=True)
+        greeks = greeks_leg(torch, hpac, x_copies[0], n, max(args.steps // 2, 3))
+
+    precision = None
+    if not args.no_structured:
+        print("[bench] precision variants", file=sys.stderr, flush=True)
+        precision = precision_leg(torch, hpac, x_copies[0], n, max(args.steps // 2, 3))
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
@@ -281,6 +380,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "structured_locality": structured,
+        "greeks": greeks,
+        "precision": precision,
     }
     print(json.dumps(line), flush=True)
 

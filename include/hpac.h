@@ -60,9 +60,20 @@ typedef int32_t hpac_status;
  *   columns, so a reused entry also reuses its gradients. */
 #define HPAC_REGION_BS_PRICE 0
 #define HPAC_REGION_BS_PRICE_GRAD 1
+/* Reduced-precision bodies of HPAC_REGION_BS_PRICE (same inputs and outputs):
+ *   _F16  every operation in FP16;
+ *   _BF16 every operation at BF16 precision (inputs and each result rounded
+ *         to the nearest BF16). */
+#define HPAC_REGION_BS_PRICE_F16 2
+#define HPAC_REGION_BS_PRICE_BF16 3
 
-/* Element type of every column of a call. */
+/* Element type of every column of a call (both inputs and outputs).
+ * HPAC_REGION_BS_PRICE takes any of the three; _F16 takes F32 or F16; _BF16
+ * takes F32 or BF16; _GRAD takes F32.  Other pairs return HPAC_EUNSUPPORTED.
+ * Half-precision columns must be 2-byte aligned, FP32 columns 4-byte. */
 #define HPAC_F32 0
+#define HPAC_F16 1
+#define HPAC_BF16 2
 
 /* Decision hierarchy (section 3.1.2, the level clause of section 3.2). */
 #define HPAC_LEVEL_THREAD 0 /* each lane decides alone                     */
@@ -161,6 +172,21 @@ hpac_status hpac_taf(const hpac_region_io *io, int32_t history_size, int32_t pre
  * A dropped item reads no input and writes no output (its output columns
  * keep their previous contents). */
 hpac_status hpac_perfo(const hpac_region_io *io, int32_t kind, int32_t param, int32_t offset);
+
+/* Greeks backward (the adjoint of HPAC_REGION_BS_PRICE_GRAD's prices).
+ * For i < n and each input j in (S, K, T, r, v):
+ *   grad_in[j][i] = grad_call[i] * dC/dx_j + grad_put[i] * dP/dx_j.
+ * hpac_bs_vjp takes the derivatives from a saved Jacobian: the 10 columns
+ * 2..11 written by the forward region (dC/dx then dP/dx), so derivatives that
+ * iACT reused in the forward pass are reused here too.
+ * hpac_bs_adjoint recomputes them from the 5 input columns instead.
+ * grad_call or grad_put may be NULL (taken as zero).  All pointers are
+ * device pointers of n floats; grad_in is a host array of 5 of them.
+ * Asynchronous on `stream`; n == 0 launches nothing. */
+hpac_status hpac_bs_vjp(int64_t n, const void *const *jacobian, const float *grad_call, const float *grad_put,
+                        void *const *grad_in, void *stream);
+hpac_status hpac_bs_adjoint(int64_t n, const void *const *in, const float *grad_call, const float *grad_put,
+                            void *const *grad_in, void *stream);
 
 /* Number of logical lanes L for n items at items_per_lane (see above);
  * -1 on invalid arguments. */

@@ -71,7 +71,11 @@ void or_bs_price(int64_t n, const double *S, const double *K, const double *T,
  * Call row: dC/dS = N(d1), dC/dK = -e^{-rT} N(d2),
  *           dC/dT = S phi(d1) v / (2 sqrt T) + r K e^{-rT} N(d2),
  *           dC/dr = K T e^{-rT} N(d2), dC/dv = S phi(d1) sqrt T.
- * Put row from parity P = C - S + K e^{-rT}. */
+ * Put row (the derivative of parity P = C - S + K e^{-rT}, with 1 - N(x)
+ * written as N(-x) so that no entry loses its relative accuracy):
+ *           dP/dS = -N(-d1), dP/dK = e^{-rT} N(-d2),
+ *           dP/dT = S phi(d1) v / (2 sqrt T) - r K e^{-rT} N(-d2),
+ *           dP/dr = -K T e^{-rT} N(-d2), dP/dv = S phi(d1) sqrt T. */
 void or_bs_jacobian(int64_t n, const double *S_, const double *K_, const double *T_,
                     const double *r_, const double *v_, double *const *J) {
 #pragma omp parallel for schedule(static)
@@ -80,16 +84,18 @@ void or_bs_jacobian(int64_t n, const double *S_, const double *K_, const double 
     double sqT = sqrt(T), vs = v * sqT;
     double d1 = (log(S / K) + (r + 0.5 * v * v) * T) / vs, d2 = d1 - vs;
     double disc = exp(-r * T), D = K * disc;
-    double Nd2 = or_ncdf(d2), pd1 = or_npdf(d1);
-    double cS = or_ncdf(d1);
-    double cK = -disc * Nd2;
-    double cT = S * pd1 * v / (2.0 * sqT) + r * D * Nd2;
-    double cR = K * T * disc * Nd2;
-    double cV = S * pd1 * sqT;
-    J[0][i] = cS;        J[1][i] = cK;         J[2][i] = cT;
-    J[3][i] = cR;        J[4][i] = cV;
-    J[5][i] = cS - 1.0;  J[6][i] = cK + disc;  J[7][i] = cT - r * D;
-    J[8][i] = cR - T * D; J[9][i] = cV;
+    double Nd2 = or_ncdf(d2), Nmd2 = or_ncdf(-d2), pd1 = or_npdf(d1);
+    double theta = S * pd1 * v / (2.0 * sqT);
+    J[0][i] = or_ncdf(d1);
+    J[1][i] = -disc * Nd2;
+    J[2][i] = theta + r * D * Nd2;
+    J[3][i] = K * T * disc * Nd2;
+    J[4][i] = S * pd1 * sqT;
+    J[5][i] = -or_ncdf(-d1);
+    J[6][i] = disc * Nmd2;
+    J[7][i] = theta - r * D * Nmd2;
+    J[8][i] = -K * T * disc * Nmd2;
+    J[9][i] = S * pd1 * sqT;
   }
 }
 

@@ -7,4 +7,5 @@ seeded synthetic input generators.  Build with
 `python -m paper_2308_16877_amd.build`.
 """
 from .hpac import (hpac_exact, hpac_iact, hpac_taf, hpac_perfo, hpac_probe_copy,  # noqa: F401
-                   hpac_num_lanes, hpac_trace_entries, hpac_last_error, hpac_abi_version)
+                   hpac_bs_vjp, hpac_bs_adjoint, hpac_num_lanes, hpac_trace_entries, hpac_last_error,
+                   hpac_abi_version)

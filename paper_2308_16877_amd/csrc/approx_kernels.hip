@@ -21,6 +21,7 @@
 // reads the total after a barrier (section 3.3).
 #include "launch.hpp"
 #include "region_bs.hpp"
+#include "region_half.hpp"
 #include "wave.hpp"
 
 #include <math.h>
@@ -35,13 +36,13 @@ enum { kSmall = 0, kLarge = 1, kIni = 2, kFini = 3 };
 template <class R>
 __device__ __forceinline__ void load_inputs(const KArgs &a, int64_t i, float (&x)[R::kIn]) {
 #pragma unroll
-  for (int j = 0; j < R::kIn; ++j) x[j] = a.in[j][i];
+  for (int j = 0; j < R::kIn; ++j) x[j] = R::io::load(a.in[j], i);
 }
 
 template <class R>
 __device__ __forceinline__ void store_outputs(const KArgs &a, int64_t i, const float (&y)[R::kOut]) {
 #pragma unroll
-  for (int o = 0; o < R::kOut; ++o) a.out[o][i] = y[o];
+  for (int o = 0; o < R::kOut; ++o) R::io::store(a.out[o], i, y[o]);
 }
 
 __device__ __forceinline__ uint32_t trace_word(int votes, int napprox, int writer, bool approx, bool voted) {
@@ -449,10 +450,7 @@ __global__ void __launch_bounds__(256) k_taf(KArgs a, int psize, float theta) {
     // speculative load of step k+1 goes unused.
     prefetch<R>(a, g, k + 1, !stable || rho == 1, xn);
     bool crit = false, voted = false;
-    if (lane_approx) {
-#pragma unroll
-      for (int o = 0; o < R::kOut; ++o) a.out[o][i] = win[H - 1][o];
-    }
+    if (lane_approx) store_outputs<R>(a, i, win[H - 1]);
     if (computes) {
       float y[R::kOut];
       R::eval(x, y);
@@ -517,81 +515,123 @@ int64_t iact_lds_bytes(int region, int block, int table_size, int tables_per_wav
   return (int64_t)(block / kWave) * tables_per_wave * table_size * E * (int64_t)sizeof(float);
 }
 
-template <class R>
-static hipError_t exact_r(const LaunchCfg &c, const KArgs &a) {
-  if (a.trace || a.counters)
-    hipLaunchKernelGGL((k_exact<R, true>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a);
-  else
-    hipLaunchKernelGGL((k_exact<R, false>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a);
-  return hipGetLastError();
+// (region, column type) -> region type.  Regions: 0 price, 1 price and
+// Jacobian, 2 price in FP16, 3 price at BF16 precision.  Column types: 0 FP32,
+// 1 FP16, 2 BF16.  The half-precision bodies pair with FP32 columns or with
+// columns of their own type; the Jacobian region takes FP32 columns only.
+bool region_dtype_supported(int region, int dtype) {
+  switch (region) {
+    case 0: return dtype >= 0 && dtype <= 2;
+    case 1: return dtype == 0;
+    case 2: return dtype == 0 || dtype == 1;
+    case 3: return dtype == 0 || dtype == 2;
+    default: return false;
+  }
 }
 
-hipError_t launch_exact(const LaunchCfg &c, const KArgs &a) {
-  return c.region == 1 ? exact_r<RegionBSPriceGrad>(c, a) : exact_r<RegionBSPrice>(c, a);
+template <class F>
+static hipError_t with_region(int region, int dtype, const F &f) {
+  switch (region * 4 + dtype) {
+    case 0: return f.template go<RegionBSPrice>();
+    case 1: return f.template go<WithIo<RegionBSPrice, IoF16>>();
+    case 2: return f.template go<WithIo<RegionBSPrice, IoBF16>>();
+    case 4: return f.template go<RegionBSPriceGrad>();
+    case 8: return f.template go<RegionBSPriceF16>();
+    case 9: return f.template go<WithIo<RegionBSPriceF16, IoF16>>();
+    case 12: return f.template go<RegionBSPriceBF16>();
+    case 14: return f.template go<WithIo<RegionBSPriceBF16, IoBF16>>();
+    default: return hipErrorInvalidValue;
+  }
 }
 
-template <class R>
-static hipError_t perfo_r(const LaunchCfg &c, const KArgs &a, int kind, int param, int offset) {
-  // the dense paths launch up to ceil(n / block) workgroups
-  if (a.trace || a.counters || param == 0 || (a.n + c.block - 1) / c.block + a.ipt > 2147483647) {
-    hipLaunchKernelGGL((k_perfo<R>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a, kind, param, offset);
+struct ExactL {
+  const LaunchCfg &c;
+  const KArgs &a;
+  template <class R>
+  hipError_t go() const {
+    if (a.trace || a.counters)
+      hipLaunchKernelGGL((k_exact<R, true>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a);
+    else
+      hipLaunchKernelGGL((k_exact<R, false>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a);
     return hipGetLastError();
   }
-  if (kind == kIni || kind == kFini) {
-    // a contiguous kept range: the exact kernel over it, one item per lane
-    const int64_t cut = ((int64_t)param * a.n) / 100;
-    KArgs b = a;
-    const int64_t lo = kind == kIni ? cut : 0;
-    b.n = a.n - cut;
-    b.ipt = 1;
-    b.L = ((b.n + 63) / 64) * 64;
-    for (int j = 0; j < R::kIn; ++j) b.in[j] = a.in[j] + lo;
-    for (int o = 0; o < R::kOut; ++o) b.out[o] = a.out[o] + lo;
-    if (b.n == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_exact<R, false>), grid_for(b, c.block), dim3(c.block), 0, c.stream, b);
+};
+
+hipError_t launch_exact(const LaunchCfg &c, const KArgs &a) { return with_region(c.region, c.dtype, ExactL{c, a}); }
+
+struct PerfoL {
+  const LaunchCfg &c;
+  const KArgs &a;
+  int kind, param, offset;
+  template <class R>
+  hipError_t go() const {
+    // the dense paths launch up to ceil(n / block) workgroups
+    if (a.trace || a.counters || param == 0 || (a.n + c.block - 1) / c.block + a.ipt > 2147483647) {
+      hipLaunchKernelGGL((k_perfo<R>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a, kind, param, offset);
+      return hipGetLastError();
+    }
+    if (kind == kIni || kind == kFini) {
+      // a contiguous kept range: the exact kernel over it, one item per lane
+      const int64_t cut = ((int64_t)param * a.n) / 100;
+      KArgs b = a;
+      const int64_t lo = kind == kIni ? cut : 0;
+      const int64_t esz = sizeof(typename R::io::elem);
+      b.n = a.n - cut;
+      b.ipt = 1;
+      b.L = ((b.n + 63) / 64) * 64;
+      for (int j = 0; j < R::kIn; ++j) b.in[j] = (const char *)a.in[j] + lo * esz;
+      for (int o = 0; o < R::kOut; ++o) b.out[o] = (char *)a.out[o] + lo * esz;
+      if (b.n == 0) return hipSuccess;
+      hipLaunchKernelGGL((k_exact<R, false>), grid_for(b, c.block), dim3(c.block), 0, c.stream, b);
+      return hipGetLastError();
+    }
+    // SMALL / LARGE: kept steps repeat with period M
+    const int M = param;
+    const int off = (int)(offset % M);
+    const int special = kind == kSmall ? ((M - 1 - off) % M + M) % M : ((M - off) % M + M) % M;
+    const int kept_per_period = kind == kSmall ? M - 1 : 1;
+    if (kept_per_period == 0) return hipSuccess;  // SMALL with M = 1 drops every step
+    const int64_t steps = (a.n + a.L - 1) / a.L;  // steps that hold items
+    // kept steps below `steps`
+    int64_t kept = (steps / M) * kept_per_period;
+    for (int64_t st = (steps / M) * M; st < steps; ++st) {
+      const int pos = (int)(st % M);
+      kept += kind == kSmall ? pos != special : pos == special;
+    }
+    if (kept == 0) return hipSuccess;
+    const int64_t bps = (a.L + c.block - 1) / c.block;
+    hipLaunchKernelGGL((k_perfo_dense<R>), dim3((unsigned)(kept * bps)), dim3(c.block), 0, c.stream, a, (int)bps,
+                       M, kept_per_period, special, kind == kLarge ? 1 : 0);
     return hipGetLastError();
   }
-  // SMALL / LARGE: kept steps repeat with period M
-  const int M = param;
-  const int off = (int)(offset % M);
-  const int special = kind == kSmall ? ((M - 1 - off) % M + M) % M : ((M - off) % M + M) % M;
-  const int kept_per_period = kind == kSmall ? M - 1 : 1;
-  if (kept_per_period == 0) return hipSuccess;  // SMALL with M = 1 drops every step
-  const int64_t steps = (a.n + a.L - 1) / a.L;  // steps that hold items
-  // kept steps below `steps`
-  int64_t kept = (steps / M) * kept_per_period;
-  for (int64_t st = (steps / M) * M; st < steps; ++st) {
-    const int pos = (int)(st % M);
-    kept += kind == kSmall ? pos != special : pos == special;
-  }
-  if (kept == 0) return hipSuccess;
-  const int64_t bps = (a.L + c.block - 1) / c.block;
-  hipLaunchKernelGGL((k_perfo_dense<R>), dim3((unsigned)(kept * bps)), dim3(c.block), 0, c.stream, a, (int)bps, M,
-                     kept_per_period, special, kind == kLarge ? 1 : 0);
-  return hipGetLastError();
-}
+};
 
 hipError_t launch_perfo(const LaunchCfg &c, const KArgs &a, int kind, int param, int offset) {
-  return c.region == 1 ? perfo_r<RegionBSPriceGrad>(c, a, kind, param, offset)
-                       : perfo_r<RegionBSPrice>(c, a, kind, param, offset);
+  return with_region(c.region, c.dtype, PerfoL{c, a, kind, param, offset});
 }
 
-template <class R>
-static hipError_t iact_r(const LaunchCfg &c, const KArgs &a, int level, int t, float thr, int tpw) {
-  const size_t lds = (size_t)iact_lds_bytes(c.region, c.block, t, tpw);
-  const dim3 g = grid_for(a, c.block), b(c.block);
-  switch (level) {
-    case kThread: hipLaunchKernelGGL((k_iact<R, kThread>), g, b, lds, c.stream, a, t, thr, tpw); break;
-    case kWaveLvl: hipLaunchKernelGGL((k_iact<R, kWaveLvl>), g, b, lds, c.stream, a, t, thr, tpw); break;
-    default: hipLaunchKernelGGL((k_iact<R, kBlock>), g, b, lds, c.stream, a, t, thr, tpw); break;
+struct IactL {
+  const LaunchCfg &c;
+  const KArgs &a;
+  int level, t;
+  float thr;
+  int tpw;
+  template <class R>
+  hipError_t go() const {
+    const size_t lds = (size_t)iact_lds_bytes(c.region, c.block, t, tpw);
+    const dim3 g = grid_for(a, c.block), b(c.block);
+    switch (level) {
+      case kThread: hipLaunchKernelGGL((k_iact<R, kThread>), g, b, lds, c.stream, a, t, thr, tpw); break;
+      case kWaveLvl: hipLaunchKernelGGL((k_iact<R, kWaveLvl>), g, b, lds, c.stream, a, t, thr, tpw); break;
+      default: hipLaunchKernelGGL((k_iact<R, kBlock>), g, b, lds, c.stream, a, t, thr, tpw); break;
+    }
+    return hipGetLastError();
   }
-  return hipGetLastError();
-}
+};
 
 hipError_t launch_iact(const LaunchCfg &c, const KArgs &a, int level, int table_size, float threshold,
                        int tables_per_wave) {
-  return c.region == 1 ? iact_r<RegionBSPriceGrad>(c, a, level, table_size, threshold, tables_per_wave)
-                       : iact_r<RegionBSPrice>(c, a, level, table_size, threshold, tables_per_wave);
+  return with_region(c.region, c.dtype, IactL{c, a, level, table_size, threshold, tables_per_wave});
 }
 
 template <class R, int LEVEL, int H>
@@ -613,20 +653,25 @@ static void taf_h(const LaunchCfg &c, const KArgs &a, int h, int p, float thr) {
   }
 }
 
-template <class R>
-static hipError_t taf_r(const LaunchCfg &c, const KArgs &a, int level, int h, int p, float thr) {
-  switch (level) {
-    case kThread: taf_h<R, kThread>(c, a, h, p, thr); break;
-    case kWaveLvl: taf_h<R, kWaveLvl>(c, a, h, p, thr); break;
-    default: taf_h<R, kBlock>(c, a, h, p, thr); break;
+struct TafL {
+  const LaunchCfg &c;
+  const KArgs &a;
+  int level, h, p;
+  float thr;
+  template <class R>
+  hipError_t go() const {
+    switch (level) {
+      case kThread: taf_h<R, kThread>(c, a, h, p, thr); break;
+      case kWaveLvl: taf_h<R, kWaveLvl>(c, a, h, p, thr); break;
+      default: taf_h<R, kBlock>(c, a, h, p, thr); break;
+    }
+    return hipGetLastError();
   }
-  return hipGetLastError();
-}
+};
 
 hipError_t launch_taf(const LaunchCfg &c, const KArgs &a, int level, int history_size, int prediction_size,
                       float threshold) {
-  return c.region == 1 ? taf_r<RegionBSPriceGrad>(c, a, level, history_size, prediction_size, threshold)
-                       : taf_r<RegionBSPrice>(c, a, level, history_size, prediction_size, threshold);
+  return with_region(c.region, c.dtype, TafL{c, a, level, history_size, prediction_size, threshold});
 }
 
 hipError_t launch_copy(const void *src, void *dst, int64_t bytes, hipStream_t stream) {

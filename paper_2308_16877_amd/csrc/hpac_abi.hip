@@ -26,7 +26,9 @@ struct RegionShape {
 
 bool region_shape(int region, RegionShape *s) {
   switch (region) {
-    case HPAC_REGION_BS_PRICE: *s = {5, 2}; return true;
+    case HPAC_REGION_BS_PRICE:
+    case HPAC_REGION_BS_PRICE_F16:
+    case HPAC_REGION_BS_PRICE_BF16: *s = {5, 2}; return true;
     case HPAC_REGION_BS_PRICE_GRAD: *s = {5, 12}; return true;
     default: return false;
   }
@@ -46,7 +48,10 @@ hpac_status check_io(const char *fn, const hpac_region_io *io, hpac::KArgs *a, h
   if (!io) return fail(HPAC_EINVAL, "%s: io is NULL", fn);
   RegionShape rs;
   if (!region_shape(io->region, &rs)) return fail(HPAC_EINVAL, "%s: unknown region %d", fn, io->region);
-  if (io->dtype != HPAC_F32) return fail(HPAC_EUNSUPPORTED, "%s: dtype %d not provided (only HPAC_F32)", fn, io->dtype);
+  if (io->dtype < HPAC_F32 || io->dtype > HPAC_BF16) return fail(HPAC_EINVAL, "%s: unknown dtype %d", fn, io->dtype);
+  if (!hpac::region_dtype_supported(io->region, io->dtype))
+    return fail(HPAC_EUNSUPPORTED, "%s: region %d does not take columns of dtype %d", fn, io->region, io->dtype);
+  const uintptr_t align = io->dtype == HPAC_F32 ? 4 : 2;
   if (io->n < 0 || io->n > kMaxItems) return fail(HPAC_EINVAL, "%s: n = %lld out of range [0, 2^40]", fn, (long long)io->n);
   if (io->n_in != rs.n_in || io->n_out != rs.n_out)
     return fail(HPAC_EINVAL, "%s: region %d takes %d inputs and %d outputs, got %d and %d", fn, io->region, rs.n_in,
@@ -60,11 +65,11 @@ hpac_status check_io(const char *fn, const hpac_region_io *io, hpac::KArgs *a, h
     if (!io->in || !io->out) return fail(HPAC_EINVAL, "%s: NULL column array", fn);
     for (int j = 0; j < rs.n_in; ++j) {
       if (!io->in[j]) return fail(HPAC_EINVAL, "%s: input column %d is NULL", fn, j);
-      if ((uintptr_t)io->in[j] % 4) return fail(HPAC_EINVAL, "%s: input column %d is not 4-byte aligned", fn, j);
+      if ((uintptr_t)io->in[j] % align) return fail(HPAC_EINVAL, "%s: input column %d is misaligned", fn, j);
     }
     for (int o = 0; o < rs.n_out; ++o) {
       if (!io->out[o]) return fail(HPAC_EINVAL, "%s: output column %d is NULL", fn, o);
-      if ((uintptr_t)io->out[o] % 4) return fail(HPAC_EINVAL, "%s: output column %d is not 4-byte aligned", fn, o);
+      if ((uintptr_t)io->out[o] % align) return fail(HPAC_EINVAL, "%s: output column %d is misaligned", fn, o);
     }
   }
   if ((num_lanes(io->n, io->items_per_lane) + block - 1) / block > kMaxBlocks)
@@ -72,14 +77,15 @@ hpac_status check_io(const char *fn, const hpac_region_io *io, hpac::KArgs *a, h
                 fn, (long long)io->n, io->items_per_lane);
   if ((uintptr_t)io->trace % 4) return fail(HPAC_EINVAL, "%s: trace is not 4-byte aligned", fn);
   if ((uintptr_t)io->counters % 8) return fail(HPAC_EINVAL, "%s: counters are not 8-byte aligned", fn);
-  for (int j = 0; j < hpac::kMaxIn; ++j) a->in[j] = j < rs.n_in && io->n > 0 ? (const float *)io->in[j] : nullptr;
-  for (int o = 0; o < hpac::kMaxOut; ++o) a->out[o] = o < rs.n_out && io->n > 0 ? (float *)io->out[o] : nullptr;
+  for (int j = 0; j < hpac::kMaxIn; ++j) a->in[j] = j < rs.n_in && io->n > 0 ? io->in[j] : nullptr;
+  for (int o = 0; o < hpac::kMaxOut; ++o) a->out[o] = o < rs.n_out && io->n > 0 ? io->out[o] : nullptr;
   a->n = io->n;
   a->ipt = io->items_per_lane;
   a->L = num_lanes(io->n, io->items_per_lane);
   a->trace = io->trace;
   a->counters = (unsigned long long *)io->counters;
   c->region = io->region;
+  c->dtype = io->dtype;
   c->block = block;
   c->stream = (hipStream_t)io->stream;
   return HPAC_OK;
@@ -176,6 +182,44 @@ hpac_status hpac_perfo(const hpac_region_io *io, int32_t kind, int32_t param, in
   if (offset < 0) return fail(HPAC_EINVAL, "%s: offset = %d must be >= 0", fn, offset);
   if (a.n == 0) return HPAC_OK;
   return hip_status(fn, hpac::launch_perfo(c, a, kind, param, offset));
+}
+
+static hpac_status check_vjp(const char *fn, int64_t n, const void *const *cols, int ncols, const float *gC,
+                             const float *gP, void *const *grad_in, hpac::VjpArgs *a) {
+  if (n < 0 || n > kMaxItems) return fail(HPAC_EINVAL, "%s: n = %lld out of range [0, 2^40]", fn, (long long)n);
+  a->n = n;
+  a->gC = gC;
+  a->gP = gP;
+  if (n == 0) return HPAC_OK;
+  if (!cols || !grad_in) return fail(HPAC_EINVAL, "%s: NULL column array", fn);
+  for (int j = 0; j < ncols; ++j)
+    if (!cols[j] || (uintptr_t)cols[j] % 4) return fail(HPAC_EINVAL, "%s: column %d is NULL or misaligned", fn, j);
+  for (int j = 0; j < 5; ++j)
+    if (!grad_in[j] || (uintptr_t)grad_in[j] % 4)
+      return fail(HPAC_EINVAL, "%s: gradient column %d is NULL or misaligned", fn, j);
+  if ((uintptr_t)gC % 4 || (uintptr_t)gP % 4) return fail(HPAC_EINVAL, "%s: upstream gradient misaligned", fn);
+  for (int j = 0; j < 5; ++j) a->gin[j] = (float *)grad_in[j];
+  return HPAC_OK;
+}
+
+hpac_status hpac_bs_vjp(int64_t n, const void *const *jacobian, const float *grad_call, const float *grad_put,
+                        void *const *grad_in, void *stream) {
+  const char *fn = "hpac_bs_vjp";
+  hpac::VjpArgs a = {};
+  hpac_status s = check_vjp(fn, n, jacobian, 10, grad_call, grad_put, grad_in, &a);
+  if (s != HPAC_OK || n == 0) return s;
+  for (int j = 0; j < 10; ++j) a.jac[j] = (const float *)jacobian[j];
+  return hip_status(fn, hpac::launch_bs_vjp(a, (hipStream_t)stream));
+}
+
+hpac_status hpac_bs_adjoint(int64_t n, const void *const *in, const float *grad_call, const float *grad_put,
+                            void *const *grad_in, void *stream) {
+  const char *fn = "hpac_bs_adjoint";
+  hpac::VjpArgs a = {};
+  hpac_status s = check_vjp(fn, n, in, 5, grad_call, grad_put, grad_in, &a);
+  if (s != HPAC_OK || n == 0) return s;
+  for (int j = 0; j < 5; ++j) a.in[j] = (const float *)in[j];
+  return hip_status(fn, hpac::launch_bs_adjoint(a, (hipStream_t)stream));
 }
 
 hpac_status hpac_probe_copy(const void *src, void *dst, int64_t bytes, void *stream) {

@@ -1,0 +1,45 @@
+// Element types of the region's columns: the kernels compute in registers
+// (float for the region interface) and convert when a column is loaded or
+// stored.  BF16 is handled as raw 16-bit patterns.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hpac {
+
+__device__ __forceinline__ float bf16_bits_to_float(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// Round to nearest, ties to even (NaN kept quiet).
+__device__ __forceinline__ uint16_t float_to_bf16_bits(float f) {
+  const uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+struct IoF32 {
+  using elem = float;
+  __device__ __forceinline__ static float load(const void *p, int64_t i) { return ((const float *)p)[i]; }
+  __device__ __forceinline__ static void store(void *p, int64_t i, float v) { ((float *)p)[i] = v; }
+};
+struct IoF16 {
+  using elem = _Float16;
+  __device__ __forceinline__ static float load(const void *p, int64_t i) { return (float)((const _Float16 *)p)[i]; }
+  __device__ __forceinline__ static void store(void *p, int64_t i, float v) { ((_Float16 *)p)[i] = (_Float16)v; }
+};
+struct IoBF16 {
+  using elem = uint16_t;
+  __device__ __forceinline__ static float load(const void *p, int64_t i) {
+    return bf16_bits_to_float(((const uint16_t *)p)[i]);
+  }
+  __device__ __forceinline__ static void store(void *p, int64_t i, float v) {
+    ((uint16_t *)p)[i] = float_to_bf16_bits(v);
+  }
+};
+
+// A region evaluated as Base with columns of element type Io.
+template <class Base, class Io>
+struct WithIo : Base {
+  using io = Io;
+};
+
+}  // namespace hpac

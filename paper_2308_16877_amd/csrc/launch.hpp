@@ -11,8 +11,8 @@ constexpr int kMaxOut = 16;
 
 // Kernel arguments of one region launch (passed by value).
 struct KArgs {
-  const float *in[kMaxIn];
-  float *out[kMaxOut];
+  const void *in[kMaxIn];  // columns of the region's element type
+  void *out[kMaxOut];
   int64_t n;     // items
   int64_t L;     // logical lanes (multiple of 64)
   int32_t ipt;   // items per lane
@@ -22,6 +22,7 @@ struct KArgs {
 
 struct LaunchCfg {
   int region;
+  int dtype;
   int block;  // workgroup lanes
   hipStream_t stream;
 };
@@ -37,5 +38,25 @@ hipError_t launch_copy(const void *src, void *dst, int64_t bytes, hipStream_t st
 
 // Bytes of LDS one iACT workgroup needs.
 int64_t iact_lds_bytes(int region, int block, int table_size, int tables_per_wave);
+
+// Whether (region, dtype) is provided.
+bool region_dtype_supported(int region, int dtype);
+
+}  // namespace hpac
+
+namespace hpac {
+
+// Greeks backward: grad_in[j] = gC * dC/dx_j + gP * dP/dx_j for the five
+// inputs, from a saved Jacobian (10 columns) or recomputed from the inputs.
+// gC or gP may be null (treated as zero).
+struct VjpArgs {
+  int64_t n;
+  const float *jac[10];  // used by the saved-Jacobian kernel
+  const float *in[5];    // used by the recomputing kernel
+  const float *gC, *gP;
+  float *gin[5];
+};
+hipError_t launch_bs_vjp(const VjpArgs &a, hipStream_t stream);
+hipError_t launch_bs_adjoint(const VjpArgs &a, hipStream_t stream);
 
 }  // namespace hpac

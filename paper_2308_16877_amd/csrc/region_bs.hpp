@@ -9,6 +9,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "io_types.hpp"
 #include "tail_q_coeffs.hpp"
 
 namespace hpac {
@@ -73,6 +74,7 @@ __device__ __forceinline__ BSCore bs_core(float S, float K, float T, float r, fl
 struct RegionBSPrice {
   static constexpr int kIn = 5;
   static constexpr int kOut = 2;
+  using io = IoF32;
   __device__ __forceinline__ static void eval(const float (&x)[kIn], float (&y)[kOut]) {
     const float S = x[0], K = x[1], T = x[2], r = x[3], v = x[4];
     const BSCore c = bs_core(S, K, T, r, v);
@@ -88,6 +90,7 @@ struct RegionBSPrice {
 struct RegionBSPriceGrad {
   static constexpr int kIn = 5;
   static constexpr int kOut = 12;
+  using io = IoF32;
   __device__ __forceinline__ static void eval(const float (&x)[kIn], float (&y)[kOut]) {
     const float S = x[0], K = x[1], T = x[2], r = x[3], v = x[4];
     const BSCore c = bs_core(S, K, T, r, v);

@@ -13,9 +13,10 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libhpac.so")
 
 HPAC_OK, HPAC_EINVAL, HPAC_EUNSUPPORTED, HPAC_EHIP = 0, -1, -2, -3
-REGION_BS_PRICE, REGION_BS_PRICE_GRAD = 0, 1
-REGION_SHAPE = {REGION_BS_PRICE: (5, 2), REGION_BS_PRICE_GRAD: (5, 12)}
-F32 = 0
+REGION_BS_PRICE, REGION_BS_PRICE_GRAD, REGION_BS_PRICE_F16, REGION_BS_PRICE_BF16 = 0, 1, 2, 3
+REGION_SHAPE = {REGION_BS_PRICE: (5, 2), REGION_BS_PRICE_GRAD: (5, 12), REGION_BS_PRICE_F16: (5, 2),
+                REGION_BS_PRICE_BF16: (5, 2)}
+F32, F16, BF16 = 0, 1, 2
 LEVEL_THREAD, LEVEL_WAVE, LEVEL_BLOCK = 0, 1, 2
 LEVELS = {"thread": LEVEL_THREAD, "wave": LEVEL_WAVE, "warp": LEVEL_WAVE, "block": LEVEL_BLOCK, "team": LEVEL_BLOCK}
 PERFO_SMALL, PERFO_LARGE, PERFO_INI, PERFO_FINI = 0, 1, 2, 3
@@ -64,7 +65,11 @@ def lib():
     L.hpac_taf.argtypes = [IO, i32, i32, f32, i32]
     L.hpac_perfo.argtypes = [IO, i32, i32, i32]
     L.hpac_probe_copy.argtypes = [vp, vp, i64, vp]
-    for f in (L.hpac_exact, L.hpac_iact, L.hpac_taf, L.hpac_perfo, L.hpac_probe_copy):
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    L.hpac_bs_vjp.argtypes = [i64, PP, vp, vp, PP, vp]
+    L.hpac_bs_adjoint.argtypes = [i64, PP, vp, vp, PP, vp]
+    for f in (L.hpac_exact, L.hpac_iact, L.hpac_taf, L.hpac_perfo, L.hpac_probe_copy, L.hpac_bs_vjp,
+              L.hpac_bs_adjoint):
         f.restype = i32
     L.hpac_num_lanes.argtypes = [i64, i32]
     L.hpac_num_lanes.restype = i64
@@ -88,12 +93,16 @@ def _addr(t):
     return t.data_ptr()
 
 
-def _check_column(t, n):
+def _dtype_code(t):
+    import torch
+    return {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}.get(t.dtype)
+
+
+def _check_column(t, n, dtype=F32):
     if isinstance(t, int):
         return
-    import torch
-    if t.dtype != torch.float32 or t.dim() != 1 or not t.is_contiguous() or t.numel() != n:
-        raise ValueError("each column must be a contiguous 1-D float32 tensor of n elements")
+    if _dtype_code(t) != dtype or t.dim() != 1 or not t.is_contiguous() or t.numel() != n:
+        raise ValueError("each column must be a contiguous 1-D tensor of n elements of the call's dtype")
 
 
 def _stream(stream, cols):
@@ -106,23 +115,28 @@ def _stream(stream, cols):
 
 
 def make_io(inputs, outputs, n=None, region=None, items_per_lane=1, block_size=0,
-            stream=None, trace=None, counters=None):
+            stream=None, trace=None, counters=None, dtype=None):
     """Build the hpac_region_io descriptor (the arrays it points to are kept
-    alive on the returned object)."""
+    alive on the returned object).  dtype defaults to the columns' type."""
     inputs, outputs = list(inputs), list(outputs)
     if region is None:
         region = REGION_BS_PRICE if len(outputs) == 2 else REGION_BS_PRICE_GRAD
     if n is None:
         n = outputs[0].numel()
+    if dtype is None:
+        first = next((c for c in inputs + outputs if not isinstance(c, int)), None)
+        dtype = F32 if first is None else _dtype_code(first)
     for c in inputs + outputs:
-        _check_column(c, n)
+        _check_column(c, n, dtype)
     ins = (ctypes.c_void_p * max(len(inputs), 1))(*[_addr(c) for c in inputs])
     outs = (ctypes.c_void_p * max(len(outputs), 1))(*[_addr(c) for c in outputs])
-    io = hpac_region_io(region, F32, n, ctypes.cast(ins, ctypes.POINTER(ctypes.c_void_p)), len(inputs),
+    io = hpac_region_io(region, dtype, n, ctypes.cast(ins, ctypes.POINTER(ctypes.c_void_p)), len(inputs),
                         ctypes.cast(outs, ctypes.POINTER(ctypes.c_void_p)), len(outputs),
                         items_per_lane, block_size, _stream(stream, inputs + outputs),
                         _addr(trace), _addr(counters))
-    io._keep = (ins, outs)
+    # keep the pointer arrays and the tensors they point into alive as long
+    # as the descriptor (a prepared launch may be replayed much later)
+    io._keep = (ins, outs, inputs, outputs, trace, counters)
     return io
 
 
@@ -181,7 +195,7 @@ class Prepared:
 def prepare(technique, inputs, outputs, **kw):
     """Prepared launch of hpac_<technique>; keyword arguments as for the
     function of that name."""
-    io_keys = ("n", "region", "items_per_lane", "block_size", "stream", "trace", "counters")
+    io_keys = ("n", "region", "items_per_lane", "block_size", "stream", "trace", "counters", "dtype")
     io_kw = {k: kw.pop(k) for k in list(kw) if k in io_keys}
     if technique == "iact":
         params = (kw.pop("table_size"), ctypes.c_float(kw.pop("threshold")), kw.pop("tables_per_wave", 1),
@@ -197,6 +211,34 @@ def prepare(technique, inputs, outputs, **kw):
     if kw:
         raise TypeError("unexpected arguments: %s" % sorted(kw))
     return Prepared(technique, inputs, outputs, params, **io_kw)
+
+
+def _ptr_array(cols):
+    arr = (ctypes.c_void_p * len(cols))(*[_addr(c) for c in cols])
+    return ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p)), arr
+
+
+def hpac_bs_vjp(jacobian, grad_call, grad_put, grad_in, n=None, stream=None):
+    """grad_in[j] = grad_call * dC/dx_j + grad_put * dP/dx_j from the 10
+    saved Jacobian columns; grad_call / grad_put may be None."""
+    n = grad_in[0].numel() if n is None else n
+    for c in list(jacobian) + list(grad_in) + [g for g in (grad_call, grad_put) if g is not None]:
+        _check_column(c, n)
+    jp, keep1 = _ptr_array(jacobian)
+    gp, keep2 = _ptr_array(grad_in)
+    st = _stream(stream, list(grad_in))
+    _call("hpac_bs_vjp", lib().hpac_bs_vjp(n, jp, _addr(grad_call), _addr(grad_put), gp, st))
+
+
+def hpac_bs_adjoint(inputs, grad_call, grad_put, grad_in, n=None, stream=None):
+    """The same contraction with the derivatives recomputed from the inputs."""
+    n = grad_in[0].numel() if n is None else n
+    for c in list(inputs) + list(grad_in) + [g for g in (grad_call, grad_put) if g is not None]:
+        _check_column(c, n)
+    ip, keep1 = _ptr_array(inputs)
+    gp, keep2 = _ptr_array(grad_in)
+    st = _stream(stream, list(grad_in))
+    _call("hpac_bs_adjoint", lib().hpac_bs_adjoint(n, ip, _addr(grad_call), _addr(grad_put), gp, st))
 
 
 def hpac_probe_copy(src, dst, nbytes, stream=None):

@@ -97,11 +97,19 @@ def test_unsupported_requests():
     # 64 tables of 32 entries for 12 outputs per wave exceed the LDS budget
     expect(hpac.HPAC_EUNSUPPORTED, hpac.hpac_iact, table_size=32, threshold=0.1, tables_per_wave=64,
            **io(outputs=[FAKE] * 12))
-    # only FP32 columns
+    # the Jacobian region takes FP32 columns only; the FP16 body does not take BF16 columns
     args = io()
-    d = hpac.make_io(args["inputs"], args["outputs"], n=args["n"], items_per_lane=4)
-    d.dtype = 2
+    d = hpac.make_io(args["inputs"], [FAKE] * 12, n=args["n"], items_per_lane=4, region=hpac.REGION_BS_PRICE_GRAD)
+    d.dtype = hpac.F16
     assert hpac.lib().hpac_exact(ctypes.byref(d)) == hpac.HPAC_EUNSUPPORTED
+    d = hpac.make_io(args["inputs"], args["outputs"], n=args["n"], items_per_lane=4, region=hpac.REGION_BS_PRICE_F16)
+    d.dtype = hpac.BF16
+    assert hpac.lib().hpac_exact(ctypes.byref(d)) == hpac.HPAC_EUNSUPPORTED
+    d.dtype = 7
+    assert hpac.lib().hpac_exact(ctypes.byref(d)) == hpac.HPAC_EINVAL
+    # half-precision columns need 2-byte alignment only
+    d = hpac.make_io([FAKE + 2] * 5, [FAKE + 2] * 2, n=0, region=hpac.REGION_BS_PRICE, dtype=hpac.F16)
+    assert hpac.lib().hpac_exact(ctypes.byref(d)) == hpac.HPAC_OK
 
 
 def test_zero_items_is_a_no_op():

@@ -159,3 +159,16 @@ def test_scales_bound_the_prices():
     C, P, sC, sP = oracle.bs_price(*x)
     assert np.all(np.abs(C) <= sC * (1 + 1e-15)) and np.all(np.abs(P) <= sP * (1 + 1e-15))
     assert np.all(sC > 0) and np.all(sP > 0)
+
+
+def test_put_row_is_the_derivative_of_parity():
+    """P = C - S + K e^{-rT}, so the put row equals the call row minus the
+    derivative of S - K e^{-rT}."""
+    x = inputs.uniform_box(5000, seed=37)
+    S, K, T, r, v = x
+    J = oracle.bs_jacobian(*x)
+    D = K * np.exp(-r * T)
+    shift = [np.ones_like(S), -np.exp(-r * T), r * D, T * D, np.zeros_like(S)]
+    for j in range(5):
+        mag = np.abs(J[j]) + np.abs(shift[j]) + 1e-300
+        assert np.all(np.abs(J[5 + j] - (J[j] - shift[j])) <= 1e-14 * mag)
