@@ -63,6 +63,16 @@ def _load():
     lib.or_perfo.argtypes = [i64, i32, i32, P, P, i32, i32, i32, P, P, P, P]
     lib.or_mape.restype = None
     lib.or_mape.argtypes = [i64, P, P, f64, P, P, P]
+    lib.or_mlp_num_params.restype = i32
+    lib.or_mlp_num_params.argtypes = []
+    lib.or_bf16.restype = f64
+    lib.or_bf16.argtypes = [f64]
+    lib.or_mlp_gelu.restype = f64
+    lib.or_mlp_gelu.argtypes = [f64]
+    lib.or_mlp_forward.restype = None
+    lib.or_mlp_forward.argtypes = [i64, P, P, P, P, P, P, i32, i32, P]
+    lib.or_mlp_loss_grad.restype = f64
+    lib.or_mlp_loss_grad.argtypes = [i64, P, P, P, P, P, P, P, i32, P]
     _lib = lib
     return lib
 
@@ -204,3 +214,51 @@ def mape(exact, approx, tau=MAPE_TAU):
     mr = ctypes.c_double(0)
     _load().or_mape(e.size, _ptr(e), _ptr(a), float(tau), ctypes.byref(m), ctypes.byref(nf), ctypes.byref(mr))
     return m.value, nf.value, mr.value
+
+
+# ---------------------------------------------------------------- surrogate
+
+def mlp_num_params():
+    return int(_load().or_mlp_num_params())
+
+
+def bf16(v):
+    """Nearest BF16 value (ties to even) of each element, as float64."""
+    f = _load().or_bf16
+    return np.vectorize(lambda a: f(float(a)))(np.asarray(v, np.float64))
+
+
+def _norm_arrays(norm):
+    return [np.ascontiguousarray(norm[k], np.float64) for k in ("in_center", "in_scale", "out_mean", "out_scale")]
+
+
+def mlp_forward(x, params, norm, round_act=True, act=True):
+    """Surrogate outputs (2, n) in FP64 on BF16-rounded weights; with
+    round_act the layer inputs are rounded to BF16 as the GPU's MFMA path does."""
+    x = _as_f64_cols(x)
+    n = x[0].size
+    w = np.ascontiguousarray(params, np.float64)
+    assert w.size == mlp_num_params()
+    c, s, mu, sc = _norm_arrays(norm)
+    y = np.empty((2, n), np.float64)
+    _load().or_mlp_forward(n, _cols(x), _ptr(w), _ptr(c), _ptr(s), _ptr(mu), _ptr(sc), int(round_act), int(act),
+                           _cols([y[0], y[1]]))
+    return y
+
+
+def mlp_loss_grad(x, targets, params, norm, act=True):
+    """(loss, gradient) of the mean squared error in normalised output space."""
+    x = _as_f64_cols(x)
+    t = _as_f64_cols(targets)
+    n = x[0].size
+    w = np.ascontiguousarray(params, np.float64)
+    c, s, mu, sc = _norm_arrays(norm)
+    g = np.empty(mlp_num_params(), np.float64)
+    loss = _load().or_mlp_loss_grad(n, _cols(x), _cols(t), _ptr(w), _ptr(c), _ptr(s), _ptr(mu), _ptr(sc),
+                                    int(act), _ptr(g))
+    return loss, g
+
+
+def gelu(v):
+    f = _load().or_mlp_gelu
+    return np.vectorize(lambda a: f(float(a)))(np.asarray(v, np.float64))

@@ -527,3 +527,136 @@ void or_mape(int64_t m, const double *exact, const double *approx, double tau,
   *n_floored = nf;
   *mape_rest = (m - nf) ? sr / (double)(m - nf) : 0.0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* R3: the MLP surrogate 5 -> 64 -> 64 -> 2 used as a further approximation  */
+/* of the Black-Scholes region.  Inputs are mapped affinely,                */
+/* xh_j = (x_j - c_j) * s_j; outputs are mapped back, y_o = yh_o * sc_o +     */
+/* mu_o.  Hidden layers use the tanh form of GELU,                          */
+/* gelu(x) = x/2 (1 + tanh(sqrt(2/pi) (x + 0.044715 x^3))).                   */
+/* Parameters are one array: W1[64][5], b1[64], W2[64][64], b2[64],          */
+/* W3[2][64], b3[2] (row = output unit).  The weights are rounded to BF16    */
+/* (round to nearest even) before use; biases are used as given.  With       */
+/* round_act the layer inputs (xh, h1, h2) are rounded to BF16 as well.      */
+/* act = 0 replaces GELU by the identity (a pin against plain products).     */
+/* ------------------------------------------------------------------------ */
+
+#define OR_NH 64
+#define OR_P (64 * 5 + 64 + 64 * 64 + 64 + 2 * 64 + 2)
+#define OR_OFF_B1 (64 * 5)
+#define OR_OFF_W2 (OR_OFF_B1 + 64)
+#define OR_OFF_B2 (OR_OFF_W2 + 64 * 64)
+#define OR_OFF_W3 (OR_OFF_B2 + 64)
+#define OR_OFF_B3 (OR_OFF_W3 + 2 * 64)
+
+int32_t or_mlp_num_params(void) { return OR_P; }
+
+/* nearest BF16 (8 significant bits), ties to even */
+double or_bf16(double v) {
+  if (v == 0.0 || !isfinite(v)) return v;
+  int e;
+  double m = frexp(v, &e); /* v = m 2^e, 0.5 <= |m| < 1 */
+  double r = nearbyint(ldexp(m, 8));
+  return ldexp(r, e - 8);
+}
+
+static double or_gelu(double x, int act) {
+  if (!act) return x;
+  const double k = sqrt(2.0 / M_PI);
+  return 0.5 * x * (1.0 + tanh(k * (x + 0.044715 * x * x * x)));
+}
+
+static double or_gelu_d(double x, int act) {
+  if (!act) return 1.0;
+  const double k = sqrt(2.0 / M_PI);
+  double u = k * (x + 0.044715 * x * x * x);
+  double t = tanh(u);
+  return 0.5 * (1.0 + t) + 0.5 * x * (1.0 - t * t) * k * (1.0 + 3.0 * 0.044715 * x * x);
+}
+
+typedef struct {
+  double xh[5], z1[OR_NH], h1[OR_NH], z2[OR_NH], h2[OR_NH], yh[2];
+} or_mlp_act;
+
+static void or_mlp_fwd1(const double *w, const double *xin, const double *c, const double *s, int round_act,
+                        int act, or_mlp_act *A) {
+  for (int j = 0; j < 5; ++j) {
+    A->xh[j] = (xin[j] - c[j]) * s[j];
+    if (round_act) A->xh[j] = or_bf16(A->xh[j]);
+  }
+  for (int o = 0; o < OR_NH; ++o) {
+    double z = w[OR_OFF_B1 + o];
+    for (int j = 0; j < 5; ++j) z += or_bf16(w[o * 5 + j]) * A->xh[j];
+    A->z1[o] = z;
+    A->h1[o] = or_gelu(z, act);
+    if (round_act) A->h1[o] = or_bf16(A->h1[o]);
+  }
+  for (int o = 0; o < OR_NH; ++o) {
+    double z = w[OR_OFF_B2 + o];
+    for (int j = 0; j < OR_NH; ++j) z += or_bf16(w[OR_OFF_W2 + o * OR_NH + j]) * A->h1[j];
+    A->z2[o] = z;
+    A->h2[o] = or_gelu(z, act);
+    if (round_act) A->h2[o] = or_bf16(A->h2[o]);
+  }
+  for (int o = 0; o < 2; ++o) {
+    double z = w[OR_OFF_B3 + o];
+    for (int j = 0; j < OR_NH; ++j) z += or_bf16(w[OR_OFF_W3 + o * OR_NH + j]) * A->h2[j];
+    A->yh[o] = z;
+  }
+}
+
+/* y (2 columns) = the surrogate's outputs for n items; x is 5 columns. */
+void or_mlp_forward(int64_t n, const double *const *x, const double *w, const double *c, const double *s,
+                    const double *mu, const double *sc, int32_t round_act, int32_t act, double *const *y) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double xin[5];
+    or_mlp_act A;
+    for (int j = 0; j < 5; ++j) xin[j] = x[j][i];
+    or_mlp_fwd1(w, xin, c, s, round_act, act, &A);
+    for (int o = 0; o < 2; ++o) y[o][i] = A.yh[o] * sc[o] + mu[o];
+  }
+}
+
+/* Mean squared error over the n items and 2 outputs in the normalised output
+ * space, L = 1/(2n) sum_i sum_o (yh_o - (t_o - mu_o)/sc_o)^2, with FP64
+ * activations, and its gradient with respect to every parameter (through
+ * the BF16 rounding of the weights as if it were the identity). */
+double or_mlp_loss_grad(int64_t n, const double *const *x, const double *const *t, const double *w,
+                        const double *c, const double *s, const double *mu, const double *sc, int32_t act,
+                        double *grad) {
+  double loss = 0.0;
+  for (int p = 0; p < OR_P; ++p) grad[p] = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    double xin[5], dy[2], dz2[OR_NH], dz1[OR_NH];
+    or_mlp_act A;
+    for (int j = 0; j < 5; ++j) xin[j] = x[j][i];
+    or_mlp_fwd1(w, xin, c, s, 0, act, &A);
+    for (int o = 0; o < 2; ++o) {
+      double e = A.yh[o] - (t[o][i] - mu[o]) / sc[o];
+      loss += e * e;
+      dy[o] = 2.0 * e / (2.0 * (double)n);
+      grad[OR_OFF_B3 + o] += dy[o];
+      for (int j = 0; j < OR_NH; ++j) grad[OR_OFF_W3 + o * OR_NH + j] += dy[o] * A.h2[j];
+    }
+    for (int j = 0; j < OR_NH; ++j) {
+      double dh = 0.0;
+      for (int o = 0; o < 2; ++o) dh += or_bf16(w[OR_OFF_W3 + o * OR_NH + j]) * dy[o];
+      dz2[j] = dh * or_gelu_d(A.z2[j], act);
+      grad[OR_OFF_B2 + j] += dz2[j];
+    }
+    for (int o = 0; o < OR_NH; ++o)
+      for (int j = 0; j < OR_NH; ++j) grad[OR_OFF_W2 + o * OR_NH + j] += dz2[o] * A.h1[j];
+    for (int j = 0; j < OR_NH; ++j) {
+      double dh = 0.0;
+      for (int o = 0; o < OR_NH; ++o) dh += or_bf16(w[OR_OFF_W2 + o * OR_NH + j]) * dz2[o];
+      dz1[j] = dh * or_gelu_d(A.z1[j], act);
+      grad[OR_OFF_B1 + j] += dz1[j];
+    }
+    for (int o = 0; o < OR_NH; ++o)
+      for (int j = 0; j < 5; ++j) grad[o * 5 + j] += dz1[o] * A.xh[j];
+  }
+  return loss / (2.0 * (double)n);
+}
+
+double or_mlp_gelu(double x) { return or_gelu(x, 1); }
