@@ -3,8 +3,8 @@
 
 Only the test suite, the smoke check and the benchmark's CPU-baseline leg
 may import this package.  The GPU library never calls it and shares no code
-with it.  The arithmetic lives in ``oracle.c`` (plain C, FP64, built with
-gcc); this module only marshals numpy arrays into it.
+with it.  The arithmetic lives in ``oracle.c`` and ``hydro.c`` (plain C, FP64, built
+with gcc); this module only marshals numpy arrays into them.
 
 Conventions: inputs are float32 columns (the region's declared input type),
 region values are float64.  ``region_values_f32out`` rounds the exact FP64
@@ -18,7 +18,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "oracle.c")
+_SRCS = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "hydro.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -30,21 +30,25 @@ GROUP_THREAD, GROUP_WAVE = 1, 64
 
 def build(force=True):
     """Compile liboracle.so with gcc (FP64, no FP contraction, OpenMP)."""
-    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+    if not force and not _stale():
         return _LIB
     tmp = _LIB + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math",
-           "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
+           "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp] + _SRCS + ["-lm"]
     subprocess.check_call(cmd)
     os.replace(tmp, _LIB)
     return _LIB
+
+
+def _stale():
+    return not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in _SRCS)
 
 
 def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if _stale():
         build()
     lib = ctypes.CDLL(_LIB)
     P = ctypes.c_void_p
@@ -73,6 +77,16 @@ def _load():
     lib.or_mlp_forward.argtypes = [i64, P, P, P, P, P, P, i32, i32, P]
     lib.or_mlp_loss_grad.restype = f64
     lib.or_mlp_loss_grad.argtypes = [i64, P, P, P, P, P, P, P, i32, P]
+    lib.hy_init.restype = ctypes.c_int
+    lib.hy_init.argtypes = [P, f64, P]
+    lib.hy_step.restype = ctypes.c_int
+    lib.hy_step.argtypes = [P, P, i32, P, P]
+    lib.hy_energy.restype = None
+    lib.hy_energy.argtypes = [P, P, P, P]
+    lib.hy_hex_volume.restype = f64
+    lib.hy_hex_volume.argtypes = [P, P]
+    lib.hy_hex_hourglass.restype = None
+    lib.hy_hex_hourglass.argtypes = [P, P, f64, f64, f64, P]
     _lib = lib
     return lib
 
@@ -262,3 +276,149 @@ def mlp_loss_grad(x, targets, params, norm, act=True):
 def gelu(v):
     f = _load().or_mlp_gelu
     return np.vectorize(lambda a: f(float(a)))(np.asarray(v, np.float64))
+
+
+# ---------------------------------------------------------------- hydro
+
+class _HyPar(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("side", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("cq", ctypes.c_double), ("cl", ctypes.c_double), ("khg", ctypes.c_double),
+                ("cfl", ctypes.c_double), ("growth", ctypes.c_double), ("dvmax", ctypes.c_double),
+                ("dt0", ctypes.c_double)]
+
+
+class _HyState(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p * 3), ("u", ctypes.c_void_p * 3), ("unew", ctypes.c_void_p * 3)] + \
+               [(f, ctypes.c_void_p) for f in ("mnode", "e", "p", "q", "c", "vol", "mass", "force", "fhg",
+                                                "weos", "rho_eos", "z_eos", "whg", "rho_hg", "z_hg", "clock")]
+
+
+class _HyTech(ctypes.Structure):
+    _fields_ = [("eos_h", ctypes.c_int32), ("eos_p", ctypes.c_int32), ("eos_theta", ctypes.c_double),
+                ("hg_h", ctypes.c_int32), ("hg_p", ctypes.c_int32), ("hg_theta", ctypes.c_double),
+                ("perfo_kind", ctypes.c_int32), ("perfo_param", ctypes.c_int32), ("perfo_ipt", ctypes.c_int32),
+                ("band", ctypes.c_double)]
+
+
+class _HyRec(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_void_p) for f in ("dec_eos", "dec_hg", "frag_eos", "frag_hg")]
+
+
+HYDRO_DEFAULTS = dict(side=1.0, gamma=1.4, cq=1.5, cl=0.25, khg=0.1, cfl=0.3, growth=1.1, dvmax=0.1, dt0=1e-7)
+
+
+class HydroState:
+    """FP64 state of the oracle hydro on an n^3 mesh (numpy arrays, the C
+    layout): x, u (3, nodes); e, p, q, c, vol, mass (elements); force, fhg
+    (24, elements); TAF windows weos (h*4, E), whg (h*24, E) and per-wave
+    counters; clock = [time, last dt]."""
+
+    def __init__(self, n, eos_h=0, hg_h=0, **par):
+        self.par = dict(HYDRO_DEFAULTS, **par)
+        self.n = int(n)
+        E, Nn = self.n ** 3, (self.n + 1) ** 3
+        W = (E + 63) // 64
+        self.E, self.Nn, self.W = E, Nn, W
+        z = lambda *sh: np.zeros(sh, np.float64)
+        self.x, self.u, self.unew = z(3, Nn), z(3, Nn), z(3, Nn)
+        self.mnode = z(Nn)
+        self.e, self.p, self.q, self.c, self.vol, self.mass = (z(E) for _ in range(6))
+        self.force, self.fhg = z(24, E), z(24, E)
+        self.weos = z(max(eos_h, 1) * 4, E)
+        self.whg = z(max(hg_h, 1) * 24, E)
+        self.rho_eos, self.z_eos, self.rho_hg, self.z_hg = (np.zeros(W, np.int32) for _ in range(4))
+        self.clock = z(2)
+        self.eos_h, self.hg_h = eos_h, hg_h
+
+    def _cpar(self):
+        return _HyPar(n=self.n, **self.par)
+
+    def _cstate(self):
+        for a in ("x", "u", "unew", "mnode", "e", "p", "q", "c", "vol", "mass", "force", "fhg", "weos", "whg",
+                  "clock"):
+            arr = getattr(self, a)
+            assert arr.dtype == np.float64 and arr.flags.c_contiguous, a
+        for a in ("rho_eos", "z_eos", "rho_hg", "z_hg"):
+            arr = getattr(self, a)
+            assert arr.dtype == np.int32 and arr.flags.c_contiguous, a
+        st = _HyState()
+        for d in range(3):
+            st.x[d] = self.x[d].ctypes.data
+            st.u[d] = self.u[d].ctypes.data
+            st.unew[d] = self.unew[d].ctypes.data
+        for f in ("mnode", "e", "p", "q", "c", "vol", "mass", "force", "fhg", "weos", "rho_eos", "z_eos", "whg",
+                  "rho_hg", "z_hg", "clock"):
+            setattr(st, f, getattr(self, f).ctypes.data)
+        return st
+
+    @property
+    def time(self):
+        return float(self.clock[0])
+
+    def copy(self):
+        c = HydroState.__new__(HydroState)
+        for k, v in self.__dict__.items():
+            c.__dict__[k] = v.copy() if isinstance(v, np.ndarray) else (dict(v) if isinstance(v, dict) else v)
+        return c
+
+
+def hydro_init(n, e_origin, eos_h=0, hg_h=0, **par):
+    """Initial Sedov state: unit density at rest, specific energy e_origin in
+    the element at the origin."""
+    s = HydroState(n, eos_h=eos_h, hg_h=hg_h, **par)
+    cp, cs = s._cpar(), s._cstate()
+    if _load().hy_init(ctypes.byref(cp), float(e_origin), ctypes.byref(cs)) != 0:
+        raise ValueError("hy_init rejected its arguments")
+    return s
+
+
+def hydro_step(s, step, eos=None, hg=None, perfo=None, band=0.0, record=False):
+    """One timestep in place.  eos / hg = (h, p, theta) for TAF on the EOS /
+    hourglass region; perfo = (kind, param, items_per_lane) for the
+    hourglass region.  With record, returns per-wave decisions and fragile
+    flags {dec_eos, dec_hg, frag_eos, frag_hg}."""
+    t = _HyTech(band=float(band))
+    if eos:
+        assert eos[0] <= s.eos_h
+        t.eos_h, t.eos_p, t.eos_theta = int(eos[0]), int(eos[1]), float(eos[2])
+    if hg:
+        assert hg[0] <= s.hg_h
+        t.hg_h, t.hg_p, t.hg_theta = int(hg[0]), int(hg[1]), float(hg[2])
+    if perfo:
+        t.perfo_kind, t.perfo_param, t.perfo_ipt = int(perfo[0]), int(perfo[1]), int(perfo[2])
+    rec, out = None, None
+    if record:
+        out = dict(dec_eos=np.full(s.W, -1, np.int8), dec_hg=np.full(s.W, -1, np.int8),
+                   frag_eos=np.zeros(s.W, np.uint8), frag_hg=np.zeros(s.W, np.uint8))
+        rec = _HyRec(**{k: v.ctypes.data for k, v in out.items()})
+    cp, cs = s._cpar(), s._cstate()
+    rc = _load().hy_step(ctypes.byref(cp), ctypes.byref(t), int(step), ctypes.byref(cs),
+                         ctypes.byref(rec) if rec is not None else None)
+    if rc != 0:
+        raise ValueError("hy_step rejected its arguments")
+    return out
+
+
+def hydro_energy(s):
+    """(internal, kinetic) energy of the state."""
+    ie, ke = ctypes.c_double(), ctypes.c_double()
+    _load().hy_energy(ctypes.byref(s._cpar()), ctypes.byref(s._cstate()), ctypes.byref(ie), ctypes.byref(ke))
+    return ie.value, ke.value
+
+
+def hex_volume(xc):
+    """Volume and its gradient (8, 3) of a hexahedron with corners xc (8, 3)
+    in the local order a + 2b + 4c."""
+    xc = np.ascontiguousarray(xc, np.float64).reshape(8, 3)
+    B = np.zeros((8, 3))
+    V = _load().hy_hex_volume(_ptr(xc), _ptr(B))
+    return V, B
+
+
+def hex_hourglass(xc, uc, rho, c, khg):
+    """Hourglass corner forces (8, 3) of one hexahedron."""
+    xc = np.ascontiguousarray(xc, np.float64).reshape(8, 3)
+    uc = np.ascontiguousarray(uc, np.float64).reshape(8, 3)
+    f = np.zeros((8, 3))
+    _load().hy_hex_hourglass(_ptr(xc), _ptr(uc), float(rho), float(c), float(khg), _ptr(f))
+    return f
