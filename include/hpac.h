@@ -188,6 +188,56 @@ hpac_status hpac_bs_vjp(int64_t n, const void *const *jacobian, const float *gra
 hpac_status hpac_bs_adjoint(int64_t n, const void *const *in, const float *grad_call, const float *grad_put,
                             void *const *grad_in, void *stream);
 
+/* ------------------------------------------------------------------------
+ * MLP surrogate: a further approximation technique for HPAC_REGION_BS_PRICE
+ * (a learned model standing in for the region inside the box it was trained
+ * on; the exact region is the fallback outside it and the judge of its
+ * error).  Network 5 -> 64 -> 64 -> 2, GELU (tanh form) on both hidden
+ * layers.  Parameters: one device array of HPAC_MLP_NUM_PARAMS floats,
+ *   W1[64][5], b1[64], W2[64][64], b2[64], W3[2][64], b3[2]
+ * (row = output unit), kept in FP32; the kernels use the weights rounded to
+ * BF16 (nearest, ties to even) and the biases in FP32.
+ * Normalisation (host values): the network sees xh_j = (x_j - in_center[j])
+ * * in_scale[j] and its outputs yh map back to y_o = yh_o * out_scale[o] +
+ * out_mean[o].
+ * ------------------------------------------------------------------------ */
+#define HPAC_MLP_NUM_PARAMS 4674
+typedef struct hpac_mlp_norm {
+  float in_center[5];
+  float in_scale[5];
+  float out_mean[2];
+  float out_scale[2];
+} hpac_mlp_norm;
+
+/* Surrogate inference over io->n items (region HPAC_REGION_BS_PRICE, FP32
+ * columns; items_per_lane, trace and counters are ignored).  An item with
+ * box_lo[j] <= x_j <= box_hi[j] for all five inputs (host arrays) gets the
+ * network's outputs, computed with BF16 MFMA and FP32 accumulation, the layer
+ * inputs rounded to BF16; every other item is appended to `queue` (device,
+ * n int32 entries, order unspecified) and gets the exact region's outputs.
+ * *queue_count (device int32) is set to the number queued.  Three launches
+ * on io->stream. */
+hpac_status hpac_surrogate(const hpac_region_io *io, const float *params, const hpac_mlp_norm *norm,
+                           const float *box_lo, const float *box_hi, int32_t *queue, int32_t *queue_count);
+
+/* Training step, part 1: the gradient of L = 1/(2 N) sum_i sum_o
+ * (yh_o(x_i) - (t_o,i - out_mean[o]) / out_scale[o])^2 over the `batch` items
+ * (columns x[5], targets t[2], device) with respect to every parameter, with
+ * FP32 activations and BF16-rounded weights (the rounding is passed through
+ * as the identity), N = loss_count.  Writes one partial gradient per 64 items:
+ * grad_partials[b * HPAC_MLP_NUM_PARAMS + p] and the partial sum of squared
+ * errors loss_partials[b], b < hpac_mlp_grad_blocks(batch). */
+int64_t hpac_mlp_grad_blocks(int64_t batch);
+hpac_status hpac_mlp_grad(int64_t batch, const float *const *x, const float *const *t, const float *params,
+                          const hpac_mlp_norm *norm, int64_t loss_count, float *grad_partials, float *loss_partials,
+                          void *stream);
+
+/* Training step, part 2: Adam (Kingma and Ba) on the FP32 parameters with
+ * the sum of `blocks` partial gradients; m and v are the caller's moment
+ * arrays (zero at step 1); step >= 1 is the bias-correction step. */
+hpac_status hpac_mlp_adam(const float *grad_partials, int64_t blocks, float *params, float *m, float *v, float lr,
+                          float beta1, float beta2, float eps, int32_t step, void *stream);
+
 /* Number of logical lanes L for n items at items_per_lane (see above);
  * -1 on invalid arguments. */
 int64_t hpac_num_lanes(int64_t n, int32_t items_per_lane);

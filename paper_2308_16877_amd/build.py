@@ -14,17 +14,20 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhpac.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["hpac_abi.hip", "approx_kernels.hip", "greeks_kernels.hip"]
+SOURCES = ["hpac_abi.hip", "approx_kernels.hip", "greeks_kernels.hip", "mlp_kernels.hip"]
 
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 instructions.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include")]
+# MFMA accumulators in ordinary VGPRs: the inference kernel converts every
+# accumulator tile to BF16 right away, so AGPR results would cost a copy each.
+EXTRA = {"mlp_kernels.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _compile(src):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + FLAGS + EXTRA.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s" % (src, r.stderr[-8000:]))

@@ -222,6 +222,101 @@ hpac_status hpac_bs_adjoint(int64_t n, const void *const *in, const float *grad_
   return hip_status(fn, hpac::launch_bs_adjoint(a, (hipStream_t)stream));
 }
 
+static hpac_status copy_norm(const char *fn, const hpac_mlp_norm *norm, float *c, float *s, float *mu,
+                             float *sc) {
+  if (!norm) return fail(HPAC_EINVAL, "%s: norm is NULL", fn);
+  for (int j = 0; j < 5; ++j) {
+    if (!isfinite(norm->in_center[j]) || !isfinite(norm->in_scale[j]))
+      return fail(HPAC_EINVAL, "%s: input normalisation must be finite", fn);
+    c[j] = norm->in_center[j];
+    s[j] = norm->in_scale[j];
+  }
+  for (int o = 0; o < 2; ++o) {
+    if (!isfinite(norm->out_mean[o]) || !isfinite(norm->out_scale[o]) || norm->out_scale[o] == 0.0f)
+      return fail(HPAC_EINVAL, "%s: output normalisation must be finite with a non-zero scale", fn);
+    mu[o] = norm->out_mean[o];
+    sc[o] = norm->out_scale[o];
+  }
+  return HPAC_OK;
+}
+
+hpac_status hpac_surrogate(const hpac_region_io *io, const float *params, const hpac_mlp_norm *norm,
+                           const float *box_lo, const float *box_hi, int32_t *queue, int32_t *queue_count) {
+  const char *fn = "hpac_surrogate";
+  hpac::KArgs ka;
+  hpac::LaunchCfg c;
+  hpac_status s = check_io(fn, io, &ka, &c);
+  if (s != HPAC_OK) return s;
+  if (io->region != HPAC_REGION_BS_PRICE || io->dtype != HPAC_F32)
+    return fail(HPAC_EUNSUPPORTED, "%s: the surrogate replaces HPAC_REGION_BS_PRICE with FP32 columns", fn);
+  if (io->n > 2147483647) return fail(HPAC_EINVAL, "%s: at most 2^31-1 items per call (int32 queue)", fn);
+  if (!box_lo || !box_hi) return fail(HPAC_EINVAL, "%s: NULL box", fn);
+  hpac::MlpArgs a = {};
+  if ((s = copy_norm(fn, norm, a.in_center, a.in_scale, a.out_mean, a.out_scale)) != HPAC_OK) return s;
+  for (int j = 0; j < 5; ++j) {
+    a.box_lo[j] = box_lo[j];
+    a.box_hi[j] = box_hi[j];
+  }
+  if (io->n == 0) return HPAC_OK;
+  if (!params || (uintptr_t)params % 4) return fail(HPAC_EINVAL, "%s: params NULL or misaligned", fn);
+  if (!queue || !queue_count || (uintptr_t)queue % 4 || (uintptr_t)queue_count % 4)
+    return fail(HPAC_EINVAL, "%s: queue or queue_count NULL or misaligned", fn);
+  a.n = io->n;
+  for (int j = 0; j < 5; ++j) a.in[j] = (const float *)io->in[j];
+  for (int o = 0; o < 2; ++o) a.out[o] = (float *)io->out[o];
+  a.params = params;
+  a.queue = queue;
+  a.queue_count = queue_count;
+  return hip_status(fn, hpac::launch_mlp_infer(a, (hipStream_t)io->stream));
+}
+
+int64_t hpac_mlp_grad_blocks(int64_t batch) { return batch < 0 ? -1 : (batch + 63) / 64; }
+
+hpac_status hpac_mlp_grad(int64_t batch, const float *const *x, const float *const *t, const float *params,
+                          const hpac_mlp_norm *norm, int64_t loss_count, float *grad_partials, float *loss_partials,
+                          void *stream) {
+  const char *fn = "hpac_mlp_grad";
+  if (batch < 0 || batch > ((int64_t)1 << 31) * 64) return fail(HPAC_EINVAL, "%s: batch out of range", fn);
+  if (loss_count < 1) return fail(HPAC_EINVAL, "%s: loss_count must be >= 1", fn);
+  hpac::MlpGradArgs a = {};
+  hpac_status s = copy_norm(fn, norm, a.in_center, a.in_scale, a.out_mean, a.out_scale);
+  if (s != HPAC_OK || batch == 0) return s;
+  if (!x || !t || !params || !grad_partials || !loss_partials) return fail(HPAC_EINVAL, "%s: NULL pointer", fn);
+  for (int j = 0; j < 5; ++j)
+    if (!x[j] || (uintptr_t)x[j] % 4) return fail(HPAC_EINVAL, "%s: input column %d NULL or misaligned", fn, j);
+  for (int o = 0; o < 2; ++o)
+    if (!t[o] || (uintptr_t)t[o] % 4) return fail(HPAC_EINVAL, "%s: target column %d NULL or misaligned", fn, o);
+  a.n = batch;
+  for (int j = 0; j < 5; ++j) a.x[j] = x[j];
+  for (int o = 0; o < 2; ++o) a.t[o] = t[o];
+  a.params = params;
+  a.inv_count = 1.0f / (float)loss_count;
+  a.grad_partials = grad_partials;
+  a.loss_partials = loss_partials;
+  return hip_status(fn, hpac::launch_mlp_grad(a, (hipStream_t)stream));
+}
+
+hpac_status hpac_mlp_adam(const float *grad_partials, int64_t blocks, float *params, float *m, float *v, float lr,
+                          float beta1, float beta2, float eps, int32_t step, void *stream) {
+  const char *fn = "hpac_mlp_adam";
+  if (blocks < 1 || !grad_partials || !params || !m || !v) return fail(HPAC_EINVAL, "%s: NULL pointer or no blocks", fn);
+  if (step < 1 || !(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+    return fail(HPAC_EINVAL, "%s: hyper-parameters out of range", fn);
+  hpac::AdamArgs a = {};
+  a.grad_partials = grad_partials;
+  a.blocks = blocks;
+  a.params = params;
+  a.m = m;
+  a.v = v;
+  a.lr = lr;
+  a.beta1 = beta1;
+  a.beta2 = beta2;
+  a.eps = eps;
+  a.bc1 = (float)(1.0 - pow((double)beta1, (double)step));
+  a.bc2 = (float)(1.0 - pow((double)beta2, (double)step));
+  return hip_status(fn, hpac::launch_mlp_adam(a, (hipStream_t)stream));
+}
+
 hpac_status hpac_probe_copy(const void *src, void *dst, int64_t bytes, void *stream) {
   const char *fn = "hpac_probe_copy";
   if (bytes < 0 || bytes % 16) return fail(HPAC_EINVAL, "%s: bytes must be a non-negative multiple of 16", fn);

@@ -41,6 +41,19 @@ class hpac_region_io(ctypes.Structure):
     ]
 
 
+class hpac_mlp_norm(ctypes.Structure):
+    _fields_ = [("in_center", ctypes.c_float * 5), ("in_scale", ctypes.c_float * 5),
+                ("out_mean", ctypes.c_float * 2), ("out_scale", ctypes.c_float * 2)]
+
+
+MLP_NUM_PARAMS = 4674
+
+
+def make_norm(in_center, in_scale, out_mean, out_scale):
+    return hpac_mlp_norm((ctypes.c_float * 5)(*map(float, in_center)), (ctypes.c_float * 5)(*map(float, in_scale)),
+                         (ctypes.c_float * 2)(*map(float, out_mean)), (ctypes.c_float * 2)(*map(float, out_scale)))
+
+
 class HpacError(RuntimeError):
     def __init__(self, status, message):
         super().__init__("%s (status %d)" % (message, status))
@@ -66,6 +79,15 @@ def lib():
     L.hpac_perfo.argtypes = [IO, i32, i32, i32]
     L.hpac_probe_copy.argtypes = [vp, vp, i64, vp]
     PP = ctypes.POINTER(ctypes.c_void_p)
+    NP = ctypes.POINTER(hpac_mlp_norm)
+    FP = ctypes.POINTER(ctypes.c_float)
+    L.hpac_surrogate.argtypes = [IO, vp, NP, FP, FP, vp, vp]
+    L.hpac_mlp_grad_blocks.argtypes = [i64]
+    L.hpac_mlp_grad_blocks.restype = i64
+    L.hpac_mlp_grad.argtypes = [i64, PP, PP, vp, NP, i64, vp, vp, vp]
+    L.hpac_mlp_adam.argtypes = [vp, i64, vp, vp, vp, f32, f32, f32, f32, i32, vp]
+    for f in (L.hpac_surrogate, L.hpac_mlp_grad, L.hpac_mlp_adam):
+        f.restype = i32
     L.hpac_bs_vjp.argtypes = [i64, PP, vp, vp, PP, vp]
     L.hpac_bs_adjoint.argtypes = [i64, PP, vp, vp, PP, vp]
     for f in (L.hpac_exact, L.hpac_iact, L.hpac_taf, L.hpac_perfo, L.hpac_probe_copy, L.hpac_bs_vjp,
@@ -239,6 +261,36 @@ def hpac_bs_adjoint(inputs, grad_call, grad_put, grad_in, n=None, stream=None):
     gp, keep2 = _ptr_array(grad_in)
     st = _stream(stream, list(grad_in))
     _call("hpac_bs_adjoint", lib().hpac_bs_adjoint(n, ip, _addr(grad_call), _addr(grad_put), gp, st))
+
+
+def hpac_surrogate(inputs, outputs, params, norm, box_lo, box_hi, queue, queue_count, stream=None):
+    """Surrogate inference with the exact region as fallback outside the box."""
+    io = make_io(inputs, outputs, region=REGION_BS_PRICE, stream=stream)
+    lo = (ctypes.c_float * 5)(*map(float, box_lo))
+    hi = (ctypes.c_float * 5)(*map(float, box_hi))
+    _call("hpac_surrogate", lib().hpac_surrogate(ctypes.byref(io), _addr(params), ctypes.byref(norm), lo, hi,
+                                                 _addr(queue), _addr(queue_count)))
+
+
+def hpac_mlp_grad_blocks(batch):
+    return lib().hpac_mlp_grad_blocks(batch)
+
+
+def hpac_mlp_grad(x, t, params, norm, loss_count, grad_partials, loss_partials, n=None, stream=None):
+    n = x[0].numel() if n is None else n
+    for c in list(x) + list(t):
+        _check_column(c, n)
+    xp, k1 = _ptr_array(x)
+    tp, k2 = _ptr_array(t)
+    st = _stream(stream, list(x))
+    _call("hpac_mlp_grad", lib().hpac_mlp_grad(n, xp, tp, _addr(params), ctypes.byref(norm), loss_count,
+                                               _addr(grad_partials), _addr(loss_partials), st))
+
+
+def hpac_mlp_adam(grad_partials, blocks, params, m, v, lr, beta1, beta2, eps, step, stream=None):
+    st = _stream(stream, [params])
+    _call("hpac_mlp_adam", lib().hpac_mlp_adam(_addr(grad_partials), blocks, _addr(params), _addr(m), _addr(v),
+                                               lr, beta1, beta2, eps, step, st))
 
 
 def hpac_probe_copy(src, dst, nbytes, stream=None):

@@ -7,8 +7,10 @@ Bars:
    half-rounded inputs, rounded to the column type: within 1e-5 of the scale
    plus one rounding of the output (2^-11 relative for FP16, 2^-8 for BF16);
  - FP16 / BF16 bodies: error relative to the scale |S N(d1)| + |K e^{-rT} N(d2)|
-   (floored at 1e-4) of the rounded inputs below 2e-2 (FP16) and 1e-1 (BF16) for every result,
-   the median below 2e-3 and 2e-2; the distribution is printed;
+   (floored at 1e-4) of the rounded inputs below 5e-2 (FP16) and 1e-1 (BF16) for every result,
+   the median below 2e-3 and 2e-2 (d1 divides ln(S/K) by v sqrt(T) >= 0.05, so one
+   rounding of the logarithm moves d1 by up to 5e-4 * 4.6 / 0.05 = 0.05); the
+   distribution is printed;
  - iACT on half columns: decisions bit-exact with the oracle on the
    half-rounded inputs.
 """
@@ -65,8 +67,8 @@ def test_fp32_body_on_half_columns(dtype):
 
 
 @pytest.mark.parametrize("region,dtype,bound,median", [
-    (hpac.REGION_BS_PRICE_F16, hpac.F32, 2e-2, 2e-3),
-    (hpac.REGION_BS_PRICE_F16, hpac.F16, 2e-2, 2e-3),
+    (hpac.REGION_BS_PRICE_F16, hpac.F32, 5e-2, 2e-3),
+    (hpac.REGION_BS_PRICE_F16, hpac.F16, 5e-2, 2e-3),
     (hpac.REGION_BS_PRICE_BF16, hpac.F32, 1e-1, 2e-2),
     (hpac.REGION_BS_PRICE_BF16, hpac.BF16, 1e-1, 2e-2),
 ])
