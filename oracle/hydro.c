@@ -38,8 +38,9 @@
  *            so internal plus kinetic energy is conserved to rounding.
  *   EOS      ideal gas p = (gamma - 1) rho e; von Neumann-Richtmyer
  *            viscosity q = rho (cq du^2 + cl c |du|) under compression,
- *            du = (V^{n+1} - V^n) / (dt (V^{n+1})^(2/3)); c = sqrt(gamma
- *            max(p, 0) / rho).
+ *            du = (dV/dt) / (V^{n+1})^(2/3), dV/dt = sum B(x^{n+1}) .
+ *            u^{n+1/2} (the volume rate, not a difference of volumes);
+ *            c = sqrt(gamma max(p, 0) / rho).
  *   dt       dt^n = min(growth dt^{n-1}, min over elements of
  *            cfl V^(1/3) / sqrt(gamma max(p + q, 0) / rho) and of
  *            dvmax V / |dV/dt|, dV/dt = sum B . u), at time n.
@@ -53,7 +54,7 @@
  *            perforation (section 3.1.5) with the grid-stride mapping of the
  *            element loop and offset = timestep.  An approximated or
  *            skipped element reuses its last computed hourglass forces.
- *   EOS region: inputs e, c, mass, V^n, the corner forces and the corner
+ *   EOS region: inputs e, c, mass, the corner forces and the corner
  *            velocities before and after the step and the new corner
  *            positions; outputs e, p, q, c.  TAF: an approximated element
  *            keeps its previous e, p, q, c.
@@ -340,11 +341,15 @@ static void hy_eos_elem(const hy_par *P, const hy_state *S, int64_t z, double dt
   double W = 0.0;
   for (int k = 0; k < 8; ++k)
     for (int d = 0; d < 3; ++d) W += S->force[(k * 3 + d) * E + z] * 0.5 * (u0[k][d] + u1[k][d]);
-  const double V1 = hy_volume(xc, NULL);
+  double B1[8][3];
+  const double V1 = hy_volume(xc, B1);
+  double vdot = 0.0;
+  for (int k = 0; k < 8; ++k)
+    for (int d = 0; d < 3; ++d) vdot += B1[k][d] * 0.5 * (u0[k][d] + u1[k][d]);
   const double m = S->mass[z];
   const double e1 = S->e[z] - dt * W / m;
   const double rho1 = m / V1;
-  const double du = (V1 - S->vol[z]) / (dt * pow(V1, 2.0 / 3.0));
+  const double du = vdot / pow(V1, 2.0 / 3.0);
   const double q1 = du < 0.0 ? rho1 * (P->cq * du * du + P->cl * S->c[z] * fabs(du)) : 0.0;
   const double p1 = (P->gamma - 1.0) * rho1 * e1;
   y[0] = e1;
