@@ -238,6 +238,90 @@ hpac_status hpac_mlp_grad(int64_t batch, const float *const *x, const float *con
 hpac_status hpac_mlp_adam(const float *grad_partials, int64_t blocks, float *params, float *m, float *v, float lr,
                           float beta1, float beta2, float eps, int32_t step, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Lagrangian hydrodynamics with approximated regions across timesteps.
+ *
+ * The paper's hydrodynamics workload is a Sedov blast on volumetric
+ * elements whose quantity of interest is the final energy at the origin,
+ * with the hourglass-force computation among the approximated kernels
+ * (section 4, Table 1 and 4.1).  This is a staggered-grid scheme of our own
+ * from published methods (FP32 state, FP64 time step): exact trilinear
+ * hexahedron volume and gradient, viscous Flanagan-Belytschko hourglass
+ * control, compatible total-energy update, ideal gas with von
+ * Neumann-Richtmyer viscosity; n^3 elements on [0, side]^3 with symmetry
+ * planes x=0, y=0, z=0, unit initial density, at rest, specific energy
+ * e_origin in the element at the origin.
+ *
+ * Two per-element regions take the paper's techniques with one element per
+ * lane (a wave is 64 consecutive elements, a TAF step is a timestep, TAF
+ * state persists in the caller's buffers between calls):
+ *  - hourglass region (24 corner forces): TAF (history 1..8) or herded
+ *    perforation (section 3.1.5) of the element loop at
+ *    perfo_items_per_lane, offset = timestep; approximated or skipped
+ *    elements reuse their last computed forces (fhg);
+ *  - EOS region (e, p, q, c): TAF; approximated elements keep their values.
+ * Layouts: element fields n^3 floats, element z = i + n (j + n k); node
+ * fields (n+1)^3 floats, node i + (n+1) (j + (n+1) k); force and fhg are
+ * [(corner * 3 + dim) * n^3 + z] with corner a + 2b + 4c for node
+ * (i+a, j+b, k+c); windows are [(slot * outputs + o) * n^3 + z];
+ * per-wave ints have hpac_hydro_waves(n) entries.  All device memory, owned
+ * by the caller.  Calls are asynchronous on `stream`; the time step stays
+ * on the device (clock), so a step never waits for the host.
+ * ------------------------------------------------------------------------ */
+typedef struct hpac_hydro_params {
+  int32_t n;     /* elements per side, 1..1000 */
+  double side;   /* edge of the domain */
+  double gamma;  /* ratio of specific heats */
+  double cq, cl; /* quadratic and linear viscosity coefficients */
+  double khg;    /* hourglass coefficient */
+  double cfl;    /* Courant factor */
+  double growth; /* largest ratio of consecutive time steps */
+  double dvmax;  /* largest relative volume change per step */
+  double dt0;    /* time step taken as "previous" by the first step */
+} hpac_hydro_params;
+
+typedef struct hpac_hydro_state {
+  float *x[3], *u[3], *unew[3]; /* node positions, velocities, velocities after a step */
+  float *mnode;                 /* node masses */
+  float *e, *p, *q, *c;         /* element specific energy, pressure, viscosity, sound speed */
+  float *vol, *mass;            /* element volume at the last force evaluation, mass */
+  float *force;                 /* corner forces, 24 n^3 */
+  float *fhg;                   /* last hourglass forces, 24 n^3 (needed when approximated) */
+  float *weos;                  /* EOS window, eos_history * 4 n^3 (EOS TAF only) */
+  int32_t *rho_eos, *z_eos;     /* per wave: countdown, pushes (EOS TAF only) */
+  float *whg;                   /* hourglass window, hg_history * 24 n^3 (hourglass TAF only) */
+  int32_t *rho_hg, *z_hg;
+  double *clock;                /* [0] time, [1] last time step */
+  double *dt_partials;          /* hpac_hydro_partials(n) doubles */
+} hpac_hydro_state;
+
+typedef struct hpac_hydro_tech {
+  int32_t eos_history, eos_prediction; /* EOS TAF; history 0 = exact */
+  float eos_threshold;
+  int32_t hg_history, hg_prediction;   /* hourglass TAF; history 0 = none */
+  float hg_threshold;
+  int32_t perfo_kind;                  /* hourglass perforation, HPAC_PERFO_* */
+  int32_t perfo_param;                 /* 0 = none */
+  int32_t perfo_items_per_lane;        /* 1..64 */
+} hpac_hydro_tech;
+
+/* Entries of the per-wave arrays and of dt_partials; -1 if n is invalid. */
+int64_t hpac_hydro_waves(int32_t n);
+int64_t hpac_hydro_partials(int32_t n);
+
+/* Initial state (every non-NULL field of *state is written; the TAF counters
+ * are zeroed, fhg is zeroed if given). */
+hpac_status hpac_hydro_init(const hpac_hydro_params *params, double e_origin, const hpac_hydro_state *state,
+                            void *stream);
+
+/* One timestep with index `step` (the perforation offset).  On return, in
+ * stream order, the velocities after the step are in state->unew: swap u
+ * and unew before the next call.  dec_eos / dec_hg (optional, device int8
+ * per wave): 0 the wave computed the region this step, 1 it approximated.
+ * Fields a technique needs must be non-NULL (HPAC_EINVAL otherwise). */
+hpac_status hpac_hydro_step(const hpac_hydro_params *params, const hpac_hydro_tech *tech, int32_t step,
+                            const hpac_hydro_state *state, int8_t *dec_eos, int8_t *dec_hg, void *stream);
+
 /* Number of logical lanes L for n items at items_per_lane (see above);
  * -1 on invalid arguments. */
 int64_t hpac_num_lanes(int64_t n, int32_t items_per_lane);

@@ -317,6 +317,156 @@ hpac_status hpac_mlp_adam(const float *grad_partials, int64_t blocks, float *par
   return hip_status(fn, hpac::launch_mlp_adam(a, (hipStream_t)stream));
 }
 
+// ------------------------------------------------------------------ hydro
+
+static bool aligned4(const void *p) { return p && (uintptr_t)p % 4 == 0; }
+
+static hpac_status check_hydro_params(const char *fn, const hpac_hydro_params *P) {
+  if (!P) return fail(HPAC_EINVAL, "%s: params is NULL", fn);
+  if (P->n < 1 || P->n > 1000) return fail(HPAC_EINVAL, "%s: n = %d out of range [1, 1000]", fn, P->n);
+  const double v[] = {P->side, P->gamma, P->cq, P->cl, P->khg, P->cfl, P->growth, P->dvmax, P->dt0};
+  for (double x : v)
+    if (!isfinite(x)) return fail(HPAC_EINVAL, "%s: non-finite parameter", fn);
+  if (!(P->side > 0) || !(P->gamma > 1) || P->cq < 0 || P->cl < 0 || P->khg < 0 || !(P->cfl > 0) ||
+      !(P->growth >= 1) || !(P->dvmax > 0) || !(P->dt0 > 0))
+    return fail(HPAC_EINVAL, "%s: parameter out of range", fn);
+  return HPAC_OK;
+}
+
+static hpac_status check_hydro_state(const char *fn, const hpac_hydro_state *S) {
+  if (!S) return fail(HPAC_EINVAL, "%s: state is NULL", fn);
+  for (int d = 0; d < 3; ++d)
+    if (!aligned4(S->x[d]) || !aligned4(S->u[d]) || !aligned4(S->unew[d]))
+      return fail(HPAC_EINVAL, "%s: node coordinate or velocity %d is NULL or misaligned", fn, d);
+  const float *f[] = {S->mnode, S->e, S->p, S->q, S->c, S->vol, S->mass, S->force};
+  for (const float *x : f)
+    if (!aligned4(x)) return fail(HPAC_EINVAL, "%s: a mesh field is NULL or misaligned", fn);
+  if (!S->clock || (uintptr_t)S->clock % 8 || !S->dt_partials || (uintptr_t)S->dt_partials % 8)
+    return fail(HPAC_EINVAL, "%s: clock or dt_partials is NULL or misaligned", fn);
+  return HPAC_OK;
+}
+
+static hpac::HydroArgs hydro_args(const hpac_hydro_params *P, const hpac_hydro_state *S) {
+  hpac::HydroArgs a = {};
+  a.n = P->n;
+  a.E = (int64_t)P->n * P->n * P->n;
+  a.Nn = (int64_t)(P->n + 1) * (P->n + 1) * (P->n + 1);
+  a.W = hpac::hydro_lanes(a.E, 1) / 64;
+  a.h = (float)(P->side / P->n);
+  a.gamma = (float)P->gamma;
+  a.gamma_d = P->gamma;
+  a.cq = (float)P->cq;
+  a.cl = (float)P->cl;
+  a.khg = (float)P->khg;
+  a.cfl = P->cfl;
+  a.growth = P->growth;
+  a.dvmax = P->dvmax;
+  for (int d = 0; d < 3; ++d) {
+    a.x[d] = S->x[d];
+    a.u[d] = S->u[d];
+    a.un[d] = S->unew[d];
+  }
+  a.mnode = S->mnode;
+  a.e = S->e;
+  a.p = S->p;
+  a.q = S->q;
+  a.c = S->c;
+  a.vol = S->vol;
+  a.mass = S->mass;
+  a.force = S->force;
+  a.fhg = S->fhg;
+  a.weos = S->weos;
+  a.rho_eos = S->rho_eos;
+  a.z_eos = S->z_eos;
+  a.whg = S->whg;
+  a.rho_hg = S->rho_hg;
+  a.z_hg = S->z_hg;
+  a.clock = S->clock;
+  a.dt_partials = S->dt_partials;
+  a.hg_ipt = 1;
+  a.hg_L = hpac::hydro_lanes(a.E, 1);
+  return a;
+}
+
+int64_t hpac_hydro_waves(int32_t n) {
+  if (n < 1 || n > 1000) return -1;
+  return hpac::hydro_lanes((int64_t)n * n * n, 1) / 64;
+}
+
+int64_t hpac_hydro_partials(int32_t n) {
+  if (n < 1 || n > 1000) return -1;
+  return hpac::hydro_partials((int64_t)n * n * n);
+}
+
+hpac_status hpac_hydro_init(const hpac_hydro_params *params, double e_origin, const hpac_hydro_state *state,
+                            void *stream) {
+  const char *fn = "hpac_hydro_init";
+  hpac_status st = check_hydro_params(fn, params);
+  if (st == HPAC_OK) st = check_hydro_state(fn, state);
+  if (st != HPAC_OK) return st;
+  if (!isfinite(e_origin) || e_origin < 0) return fail(HPAC_EINVAL, "%s: e_origin must be finite and >= 0", fn);
+  if ((state->rho_eos == NULL) != (state->z_eos == NULL) || (state->rho_hg == NULL) != (state->z_hg == NULL))
+    return fail(HPAC_EINVAL, "%s: a countdown array without its push-count array", fn);
+  if ((state->fhg && !aligned4(state->fhg)) || (state->rho_eos && !aligned4(state->rho_eos)) ||
+      (state->z_eos && !aligned4(state->z_eos)) || (state->rho_hg && !aligned4(state->rho_hg)) ||
+      (state->z_hg && !aligned4(state->z_hg)))
+    return fail(HPAC_EINVAL, "%s: misaligned optional field", fn);
+  const hpac::HydroArgs a = hydro_args(params, state);
+  return hip_status(fn, hpac::launch_hydro_init(a, e_origin, params->dt0, (hipStream_t)stream));
+}
+
+hpac_status hpac_hydro_step(const hpac_hydro_params *params, const hpac_hydro_tech *tech, int32_t step,
+                            const hpac_hydro_state *state, int8_t *dec_eos, int8_t *dec_hg, void *stream) {
+  const char *fn = "hpac_hydro_step";
+  hpac_status st = check_hydro_params(fn, params);
+  if (st == HPAC_OK) st = check_hydro_state(fn, state);
+  if (st != HPAC_OK) return st;
+  if (!tech) return fail(HPAC_EINVAL, "%s: tech is NULL", fn);
+  if (step < 0) return fail(HPAC_EINVAL, "%s: step = %d must be >= 0", fn, step);
+  const hpac_hydro_tech &T = *tech;
+  if (T.eos_history < 0 || T.eos_history > 8 || T.hg_history < 0 || T.hg_history > 8)
+    return fail(HPAC_EINVAL, "%s: history sizes must be in [0, 8]", fn);
+  if ((T.eos_history && T.eos_prediction < 1) || (T.hg_history && T.hg_prediction < 1))
+    return fail(HPAC_EINVAL, "%s: prediction sizes must be >= 1", fn);
+  if (!(T.eos_threshold >= 0.0f) || !isfinite(T.eos_threshold) || !(T.hg_threshold >= 0.0f) ||
+      !isfinite(T.hg_threshold))
+    return fail(HPAC_EINVAL, "%s: thresholds must be finite and >= 0", fn);
+  if (T.perfo_kind < HPAC_PERFO_SMALL || T.perfo_kind > HPAC_PERFO_FINI || T.perfo_param < 0)
+    return fail(HPAC_EINVAL, "%s: bad perforation kind or parameter", fn);
+  if ((T.perfo_kind == HPAC_PERFO_INI || T.perfo_kind == HPAC_PERFO_FINI) && T.perfo_param > 100)
+    return fail(HPAC_EINVAL, "%s: perforation percentage %d > 100", fn, T.perfo_param);
+  if (T.perfo_param && (T.perfo_items_per_lane < 1 || T.perfo_items_per_lane > 64))
+    return fail(HPAC_EINVAL, "%s: perfo_items_per_lane must be in [1, 64]", fn);
+  if (T.hg_history && T.perfo_param) return fail(HPAC_EINVAL, "%s: TAF and perforation on the hourglass region", fn);
+  if (T.eos_history && (!aligned4(state->weos) || !aligned4(state->rho_eos) || !aligned4(state->z_eos)))
+    return fail(HPAC_EINVAL, "%s: EOS TAF needs weos, rho_eos and z_eos", fn);
+  if (T.hg_history && (!aligned4(state->whg) || !aligned4(state->rho_hg) || !aligned4(state->z_hg)))
+    return fail(HPAC_EINVAL, "%s: hourglass TAF needs whg, rho_hg and z_hg", fn);
+  if ((T.hg_history || T.perfo_param) && !aligned4(state->fhg))
+    return fail(HPAC_EINVAL, "%s: an approximated hourglass region needs fhg", fn);
+  hpac::HydroArgs a = hydro_args(params, state);
+  a.step = step;
+  a.dec_eos = T.eos_history ? dec_eos : nullptr;
+  a.dec_hg = T.hg_history ? dec_hg : nullptr;
+  a.eos_h = T.eos_history;
+  a.eos_p = T.eos_prediction;
+  a.eos_theta = T.eos_threshold;
+  a.hg_h = T.hg_history;
+  a.hg_p = T.hg_prediction;
+  a.hg_theta = T.hg_threshold;
+  a.perfo_kind = T.perfo_kind;
+  a.perfo_param = T.perfo_param;
+  int mode = hpac::kHgExact;
+  if (T.hg_history) {
+    mode = hpac::kHgTaf;
+  } else if (T.perfo_param) {
+    mode = hpac::kHgPerfo;
+    a.hg_ipt = T.perfo_items_per_lane;
+    a.hg_L = hpac::hydro_lanes(a.E, a.hg_ipt);
+  }
+  return hip_status(fn, hpac::launch_hydro_step(a, mode, T.eos_history > 0, (hipStream_t)stream));
+}
+
 hpac_status hpac_probe_copy(const void *src, void *dst, int64_t bytes, void *stream) {
   const char *fn = "hpac_probe_copy";
   if (bytes < 0 || bytes % 16) return fail(HPAC_EINVAL, "%s: bytes must be a non-negative multiple of 16", fn);

@@ -1,0 +1,553 @@
+// Lagrangian hydrodynamics on a structured hexahedral mesh (a Sedov point
+// blast) with the paper's techniques applied across timesteps to two
+// per-element regions: the hourglass-force region (TAF or herded
+// perforation) and the EOS region (TAF).  The paper approximates the
+// hourglass computation of its hydrodynamics proxy and reports the final
+// origin energy as quantity of interest (section 4, Table 1 and 4.1).
+//
+// Scheme (our own, from published methods; FP32 state, FP64 time step):
+//   n^3 elements on [0, side]^3, (n+1)^3 nodes, symmetry planes x=0, y=0,
+//   z=0, free outer faces.  Element (i,j,k), corner a + 2b + 4c is node
+//   (i+a, j+b, k+c); reference coordinates s = (2a-1, 2b-1, 2c-1).
+//   k_hydro_force  per element: volume V and its gradient B = dV/dx from the
+//                  2x2x2 Gauss rule (exact for a trilinear hexahedron);
+//                  corner forces (p + q) B + hourglass forces (viscous
+//                  Flanagan-Belytschko form); the element's FP64 time-step
+//                  bound, reduced per workgroup.
+//   k_hydro_dt     dt = min(growth * previous dt, all bounds); time += dt.
+//   k_hydro_node   per node: gather of the adjacent corner forces in corner
+//                  order (no atomics), u' = u + dt F / M, zero normal
+//                  velocity on the symmetry planes, x += dt (u + u') / 2.
+//   k_hydro_eos    per element: compatible energy update m de = -dt
+//                  sum F . (u + u')/2 (Caramana et al. 1998), ideal-gas
+//                  pressure, von Neumann-Richtmyer viscosity from the
+//                  volume rate sum B(x') . (u + u')/2, sound speed.
+// One element per lane, so a wave is 64 consecutive elements and a TAF
+// "step" is a timestep: windows live in HBM, the countdown and push count of
+// each wave in one int each, read once per wave and written by its first
+// lane.  An approximate wave-step of the EOS region reads only its
+// countdown; one of the hourglass region reads the last hourglass forces
+// instead of computing them.
+#include "launch.hpp"
+#include "wave.hpp"
+
+namespace hpac {
+
+namespace {
+
+constexpr float kGauss = 0.577350269189625765f;  // 1/sqrt(3)
+
+struct DnTable {
+  float v[8][8][3];  // dN_c/dxi_j at Gauss point q: v[q][c][j]
+};
+constexpr float sgnf(int c, int d) { return ((c >> d) & 1) ? 1.0f : -1.0f; }
+constexpr DnTable make_dn() {
+  DnTable t{};
+  for (int q = 0; q < 8; ++q)
+    for (int c = 0; c < 8; ++c)
+      for (int j = 0; j < 3; ++j) {
+        float v = 0.125f * sgnf(c, j);
+        for (int l = 0; l < 3; ++l)
+          if (l != j) v *= 1.0f + sgnf(c, l) * sgnf(q, l) * kGauss;
+        t.v[q][c][j] = v;
+      }
+  return t;
+}
+
+// The 4 edges along direction j: lower corner of edge e.
+constexpr int edge_lo(int j, int e) {
+  // insert a zero bit at position j into the 2-bit number e
+  return j == 0 ? (e << 1) : j == 1 ? ((e & 2) << 1) | (e & 1) : e;
+}
+struct EdgeW {
+  float v[8][3][4];  // weight of edge e along j in J[.][j] at Gauss point q
+};
+constexpr EdgeW make_edge_w() {
+  EdgeW t{};
+  for (int q = 0; q < 8; ++q)
+    for (int j = 0; j < 3; ++j)
+      for (int e = 0; e < 4; ++e) {
+        const int c = edge_lo(j, e);
+        float v = 0.125f;
+        for (int l = 0; l < 3; ++l)
+          if (l != j) v *= 1.0f + sgnf(c, l) * sgnf(q, l) * kGauss;
+        t.v[q][j][e] = v;
+      }
+  return t;
+}
+
+// Hourglass base vectors: products of reference coordinates.
+constexpr float gamma_base(int a, int k) {
+  return a == 0 ? sgnf(k, 1) * sgnf(k, 2)
+       : a == 1 ? sgnf(k, 0) * sgnf(k, 2)
+       : a == 2 ? sgnf(k, 0) * sgnf(k, 1)
+                : sgnf(k, 0) * sgnf(k, 1) * sgnf(k, 2);
+}
+
+// Volume (2x2x2 Gauss rule of det J) and, with kGrad, B = dV/dx.  J is
+// formed from edge differences, which neighbouring FP32 coordinates give
+// almost exactly, instead of from the coordinates themselves, whose
+// magnitude far exceeds an element's size.
+template <bool kGrad>
+__device__ __forceinline__ float hex_volume(const float (&x)[8][3], float (&B)[8][3]) {
+  constexpr DnTable T = make_dn();
+  constexpr EdgeW EW = make_edge_w();
+  float D[3][4][3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) D[j][e][i] = x[edge_lo(j, e) | (1 << j)][i] - x[edge_lo(j, e)][i];
+  float V = 0.0f;
+  if (kGrad) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) B[c][i] = 0.0f;
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    float J[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        float s = 0.0f;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) s = __builtin_fmaf(D[j][e][i], EW.v[q][j][e], s);
+        J[i][j] = s;
+      }
+    float cof[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+        cof[i][j] = J[i1][j1] * J[i2][j2] - J[i1][j2] * J[i2][j1];
+      }
+    V += J[0][0] * cof[0][0] + J[0][1] * cof[0][1] + J[0][2] * cof[0][2];
+    if (kGrad) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) B[c][i] = __builtin_fmaf(cof[i][j], T.v[q][c][j], B[c][i]);
+    }
+  }
+  return V;
+}
+
+__device__ __forceinline__ void hourglass(const float (&x)[8][3], const float (&u)[8][3], const float (&B)[8][3],
+                                          float V, float rho, float c, float khg, float (&f)[8][3]) {
+  const float inv_v = 1.0f / V;
+  float h[4][3];
+  float gam[4][8];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    float gx[3];
+    // both sums vanish on constants (the base vectors and the hourglass
+    // vectors sum to zero), so they are taken relative to corner 0
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      float s = 0.0f;
+#pragma unroll
+      for (int k = 1; k < 8; ++k) s = __builtin_fmaf(gamma_base(a, k), x[k][i] - x[0][i], s);
+      gx[i] = s * inv_v;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      gam[a][k] = gamma_base(a, k) - (gx[0] * B[k][0] + gx[1] * B[k][1] + gx[2] * B[k][2]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      float s = 0.0f;
+#pragma unroll
+      for (int k = 1; k < 8; ++k) s = __builtin_fmaf(gam[a][k], u[k][i] - u[0][i], s);
+      h[a][i] = s;
+    }
+  }
+  const float cv = cbrtf(V);
+  const float coef = -(khg * 0.125f) * rho * c * (cv * cv);
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      float s = 0.0f;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) s = __builtin_fmaf(gam[a][k], h[a][i], s);
+      f[k][i] = coef * s;
+    }
+}
+
+struct ElemIdx {
+  int64_t z;
+  int64_t node0;  // node of corner 0
+  __device__ ElemIdx(int64_t z_, int n) : z(z_) {
+    const int64_t m = n + 1;
+    const int64_t i = z % n, j = (z / n) % n, k = z / ((int64_t)n * n);
+    node0 = i + m * (j + m * k);
+  }
+  __device__ int64_t node(int c, int n) const {
+    const int64_t m = n + 1;
+    return node0 + (c & 1) + m * (((c >> 1) & 1) + m * ((c >> 2) & 1));
+  }
+};
+
+__device__ __forceinline__ void gather3(const float *const *src, const ElemIdx &e, int n, float (&v)[8][3]) {
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int64_t nd = e.node(c, n);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) v[c][d] = src[d][nd];
+  }
+}
+
+// Whether the RSD of every output over the h window slots is below theta:
+// slot `fresh` holds y (not yet visible in memory), the others are read from
+// the window.  Division-free, in FP64 (see rsd_below in approx_kernels.hip).
+template <int NO>
+__device__ __forceinline__ bool window_rsd_below(const float *win, int64_t E, int64_t z, int h, int fresh,
+                                                 const float (&y)[NO], double th2, bool th_pos) {
+  bool ok = true;
+#pragma unroll
+  for (int o = 0; o < NO; ++o) {
+    double s = 0.0;
+    for (int q = 0; q < h; ++q) s += (double)(q == fresh ? y[o] : win[((int64_t)q * NO + o) * E + z]);
+    double D = 0.0;
+    for (int q = 0; q < h; ++q) {
+      const double d = (double)h * (double)(q == fresh ? y[o] : win[((int64_t)q * NO + o) * E + z]) - s;
+      D = __builtin_fma(d, d, D);
+    }
+    ok = ok && (D == 0.0 ? th_pos : D < (double)h * th2 * (s * s));
+  }
+  return ok;
+}
+
+__device__ __forceinline__ double block_min(double v, double *red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  return red[0];
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ init
+
+__global__ void __launch_bounds__(256) k_hydro_init_elem(HydroArgs a, double e_origin) {
+  const int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= a.E) return;
+  const int n = a.n;
+  const int64_t i = z % n, j = (z / n) % n, k = z / ((int64_t)n * n);
+  float x[8][3], B[8][3];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    x[c][0] = a.h * (float)(i + (c & 1));
+    x[c][1] = a.h * (float)(j + ((c >> 1) & 1));
+    x[c][2] = a.h * (float)(k + ((c >> 2) & 1));
+  }
+  const float V = hex_volume<false>(x, B);
+  const float rho0 = 1.0f;
+  a.vol[z] = V;
+  a.mass[z] = rho0 * V;
+  const float e = z == 0 ? (float)e_origin : 0.0f;
+  const float p = (a.gamma - 1.0f) * rho0 * e;
+  a.e[z] = e;
+  a.p[z] = p;
+  a.q[z] = 0.0f;
+  a.c[z] = sqrtf(a.gamma * fmaxf(p, 0.0f) / rho0);
+  if (a.fhg)
+    for (int o = 0; o < 24; ++o) a.fhg[o * a.E + z] = 0.0f;
+}
+
+__global__ void __launch_bounds__(256) k_hydro_init_node(HydroArgs a) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= a.Nn) return;
+  const int n = a.n;
+  const int64_t m = n + 1;
+  const int64_t i = v % m, j = (v / m) % m, k = v / (m * m);
+  a.x[0][v] = a.h * (float)i;
+  a.x[1][v] = a.h * (float)j;
+  a.x[2][v] = a.h * (float)k;
+  float M = 0.0f;
+  for (int c = 0; c < 8; ++c) {
+    const int64_t ei = i - (c & 1), ej = j - ((c >> 1) & 1), ek = k - ((c >> 2) & 1);
+    if (ei < 0 || ej < 0 || ek < 0 || ei >= n || ej >= n || ek >= n) continue;
+    M += a.mass[ei + n * (ej + (int64_t)n * ek)] * 0.125f;
+  }
+  a.mnode[v] = M;
+  for (int d = 0; d < 3; ++d) {
+    a.u[d][v] = 0.0f;
+    a.un[d][v] = 0.0f;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_hydro_init_waves(HydroArgs a, double dt0) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w == 0) {
+    a.clock[0] = 0.0;
+    a.clock[1] = dt0;
+  }
+  if (w >= a.W) return;
+  if (a.rho_eos) a.rho_eos[w] = 0, a.z_eos[w] = 0;
+  if (a.rho_hg) a.rho_hg[w] = 0, a.z_hg[w] = 0;
+}
+
+// ------------------------------------------------------------------ force
+
+template <int HG>
+__global__ void __launch_bounds__(256) k_hydro_force(HydroArgs a) {
+  __shared__ double red[256];
+  const int n = a.n;
+  const int64_t E = a.E;
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = lane_id();
+  double bound = INFINITY;
+  for (int k = 0; k < a.hg_ipt; ++k) {
+    const int64_t z = l + (int64_t)k * a.hg_L;
+    const bool active = z < E;
+    const int64_t w = l >> 6;  // TAF: one element per lane
+    bool compute_hg = true;
+    int rho = 0, pushes = 0;
+    if (HG == kHgPerfo) {
+      const int M = a.perfo_param;
+      if (M > 0) {
+        switch (a.perfo_kind) {
+          case 0: compute_hg = (int)(((int64_t)k + a.step) % M) != M - 1; break;
+          case 1: compute_hg = (int)(((int64_t)k + a.step) % M) == 0; break;
+          case 2: compute_hg = z >= (int64_t)M * E / 100; break;
+          default: compute_hg = z < E - (int64_t)M * E / 100; break;
+        }
+      }
+    }
+    if (HG == kHgTaf && w < a.W) {
+      rho = a.rho_hg[w];
+      pushes = a.z_hg[w];
+      compute_hg = rho <= 0;
+    }
+    bool crit = false, voted = false;
+    if (active) {
+      const ElemIdx ei(z, n);
+      float x[8][3], u[8][3], B[8][3], f[8][3];
+      gather3(a.x, ei, n, x);
+      gather3(a.u, ei, n, u);
+      const float V = hex_volume<true>(x, B);
+      a.vol[z] = V;
+      const float rho_e = a.mass[z] / V;
+      if (compute_hg) {
+        hourglass(x, u, B, V, rho_e, a.c[z], a.khg, f);
+        if (HG != kHgExact)
+#pragma unroll
+          for (int o = 0; o < 24; ++o) a.fhg[o * E + z] = f[o / 3][o % 3];
+      } else {
+#pragma unroll
+        for (int o = 0; o < 24; ++o) f[o / 3][o % 3] = a.fhg[o * E + z];
+      }
+      const float pq = a.p[z] + a.q[z];
+      float vdot = 0.0f;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          a.force[(c * 3 + d) * E + z] = __builtin_fmaf(pq, B[c][d], f[c][d]);
+          if (c > 0) vdot = __builtin_fmaf(B[c][d], u[c][d] - u[0][d], vdot);
+        }
+      // time-step bound in FP64
+      const double Vd = (double)V, rd = (double)a.mass[z] / Vd;
+      const double ceff2 = a.gamma_d * fmax((double)pq, 0.0) / rd;
+      double b = ceff2 > 0.0 ? a.cfl * cbrt(Vd) / sqrt(ceff2) : INFINITY;
+      if (vdot != 0.0f) b = fmin(b, a.dvmax * Vd / fabs((double)vdot));
+      bound = fmin(bound, b);
+      if (HG == kHgTaf && compute_hg) {
+        const int slot = pushes % a.hg_h;
+        float y[24];
+#pragma unroll
+        for (int o = 0; o < 24; ++o) {
+          y[o] = f[o / 3][o % 3];
+          a.whg[((int64_t)slot * 24 + o) * E + z] = y[o];
+        }
+        if (pushes + 1 >= a.hg_h) {
+          voted = true;
+          const double th = (double)a.hg_theta;
+          crit = window_rsd_below<24>(a.whg, E, z, a.hg_h, slot, y, th * th, th > 0.0);
+        }
+      }
+    }
+    if (HG == kHgTaf && w < a.W) {
+      const uint64_t amask = ballot(active);
+      const uint64_t vmask = ballot(crit);
+      const bool any_vote = ballot(voted) != 0;
+      if (lane == 0) {
+        if (!compute_hg) {
+          a.rho_hg[w] = rho - 1;
+        } else {
+          a.z_hg[w] = pushes + 1;
+          if (any_vote && majority(popc(vmask), popc(amask))) a.rho_hg[w] = a.hg_p;
+        }
+        if (a.dec_hg) a.dec_hg[w] = compute_hg ? 0 : 1;
+      }
+    }
+  }
+  const double m = block_min(bound, red);
+  if (threadIdx.x == 0) a.dt_partials[blockIdx.x] = m;
+}
+
+// ------------------------------------------------------------------ dt
+
+__global__ void __launch_bounds__(256) k_hydro_dt(HydroArgs a, int64_t parts) {
+  __shared__ double red[256];
+  double m = INFINITY;
+  for (int64_t b = threadIdx.x; b < parts; b += blockDim.x) m = fmin(m, a.dt_partials[b]);
+  m = block_min(m, red);
+  if (threadIdx.x == 0) {
+    const double dt = fmin(m, a.growth * a.clock[1]);
+    a.clock[0] += dt;
+    a.clock[1] = dt;
+  }
+}
+
+// ------------------------------------------------------------------ nodes
+
+__global__ void __launch_bounds__(256) k_hydro_node(HydroArgs a) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= a.Nn) return;
+  const int n = a.n;
+  const int64_t m = n + 1, E = a.E;
+  const int64_t i = v % m, j = (v / m) % m, k = v / (m * m);
+  float F[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int64_t ei = i - (c & 1), ej = j - ((c >> 1) & 1), ek = k - ((c >> 2) & 1);
+    if (ei < 0 || ej < 0 || ek < 0 || ei >= n || ej >= n || ek >= n) continue;
+    const int64_t z = ei + n * (ej + (int64_t)n * ek);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) F[d] += a.force[(c * 3 + d) * E + z];
+  }
+  const float dt = (float)a.clock[1];
+  const float inv_m = 1.0f / a.mnode[v];
+  const int64_t idx[3] = {i, j, k};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float u0 = a.u[d][v];
+    float u1 = __builtin_fmaf(dt, F[d] * inv_m, u0);
+    if (idx[d] == 0) u1 = 0.0f;
+    a.un[d][v] = u1;
+    a.x[d][v] = __builtin_fmaf(dt, 0.5f * (u0 + u1), a.x[d][v]);
+  }
+}
+
+// ------------------------------------------------------------------ EOS
+
+template <bool kTaf>
+__global__ void __launch_bounds__(256) k_hydro_eos(HydroArgs a) {
+  const int n = a.n;
+  const int64_t E = a.E;
+  const int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t w = z >> 6;
+  if (w >= a.W) return;  // whole waves past the last element
+  const int lane = lane_id();
+  const bool active = z < E;
+  int pushes = 0;
+  if (kTaf) {
+    const int rho = a.rho_eos[w];
+    if (rho > 0) {
+      if (lane == 0) {
+        a.rho_eos[w] = rho - 1;
+        if (a.dec_eos) a.dec_eos[w] = 1;
+      }
+      return;
+    }
+    pushes = a.z_eos[w];
+  }
+  bool crit = false, voted = false;
+  if (active) {
+    const ElemIdx ei(z, n);
+    float x[8][3], u0[8][3], u1[8][3], B[8][3];
+    gather3(a.x, ei, n, x);
+    gather3(a.u, ei, n, u0);
+    gather3(a.un, ei, n, u1);
+    float W = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) W = __builtin_fmaf(a.force[(c * 3 + d) * E + z], 0.5f * (u0[c][d] + u1[c][d]), W);
+    const float V1 = hex_volume<true>(x, B);
+    // volume rate sum B . u (B sums to zero, so relative to corner 0)
+    float vdot = 0.0f;
+#pragma unroll
+    for (int c = 1; c < 8; ++c)
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        vdot = __builtin_fmaf(B[c][d], 0.5f * (u0[c][d] + u1[c][d]) - 0.5f * (u0[0][d] + u1[0][d]), vdot);
+    const float dt = (float)a.clock[1];
+    const float m = a.mass[z];
+    const float e1 = a.e[z] - dt * W / m;
+    const float rho1 = m / V1;
+    const float cv = cbrtf(V1);
+    const float du = vdot / (cv * cv);
+    const float q1 = du < 0.0f ? rho1 * (a.cq * du * du + a.cl * a.c[z] * fabsf(du)) : 0.0f;
+    const float p1 = (a.gamma - 1.0f) * rho1 * e1;
+    const float c1 = sqrtf(a.gamma * fmaxf(p1, 0.0f) / rho1);
+    a.e[z] = e1;
+    a.p[z] = p1;
+    a.q[z] = q1;
+    a.c[z] = c1;
+    if (kTaf) {
+      const int slot = pushes % a.eos_h;
+      const float y[4] = {e1, p1, q1, c1};
+#pragma unroll
+      for (int o = 0; o < 4; ++o) a.weos[((int64_t)slot * 4 + o) * E + z] = y[o];
+      if (pushes + 1 >= a.eos_h) {
+        voted = true;
+        const double th = (double)a.eos_theta;
+        crit = window_rsd_below<4>(a.weos, E, z, a.eos_h, slot, y, th * th, th > 0.0);
+      }
+    }
+  }
+  if (kTaf) {
+    const uint64_t amask = ballot(active);
+    const uint64_t vmask = ballot(crit);
+    const bool any_vote = ballot(voted) != 0;
+    if (lane == 0) {
+      a.z_eos[w] = pushes + 1;
+      if (any_vote && majority(popc(vmask), popc(amask))) a.rho_eos[w] = a.eos_p;
+      if (a.dec_eos) a.dec_eos[w] = 0;
+    }
+  }
+}
+
+// --------------------------------------------------------------- launchers
+
+int64_t hydro_lanes(int64_t E, int ipt) { return 64 * (((E + ipt - 1) / ipt + 63) / 64); }
+
+int64_t hydro_partials(int64_t E) { return (hydro_lanes(E, 1) + 255) / 256; }
+
+hipError_t launch_hydro_init(const HydroArgs &a, double e_origin, double dt0, hipStream_t s) {
+  hipLaunchKernelGGL(k_hydro_init_elem, dim3((unsigned)((a.E + 255) / 256)), dim3(256), 0, s, a, e_origin);
+  hipLaunchKernelGGL(k_hydro_init_node, dim3((unsigned)((a.Nn + 255) / 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_hydro_init_waves, dim3((unsigned)((a.W + 255) / 256)), dim3(256), 0, s, a, dt0);
+  return hipGetLastError();
+}
+
+hipError_t launch_hydro_step(const HydroArgs &a, int hg_mode, bool eos_taf, hipStream_t s) {
+  const unsigned fblocks = (unsigned)((a.hg_L + 255) / 256);
+  switch (hg_mode) {
+    case kHgExact: hipLaunchKernelGGL(k_hydro_force<kHgExact>, dim3(fblocks), dim3(256), 0, s, a); break;
+    case kHgTaf: hipLaunchKernelGGL(k_hydro_force<kHgTaf>, dim3(fblocks), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL(k_hydro_force<kHgPerfo>, dim3(fblocks), dim3(256), 0, s, a); break;
+  }
+  hipLaunchKernelGGL(k_hydro_dt, dim3(1), dim3(256), 0, s, a, (int64_t)fblocks);
+  hipLaunchKernelGGL(k_hydro_node, dim3((unsigned)((a.Nn + 255) / 256)), dim3(256), 0, s, a);
+  const unsigned eblocks = (unsigned)((hydro_lanes(a.E, 1) + 255) / 256);
+  if (eos_taf)
+    hipLaunchKernelGGL(k_hydro_eos<true>, dim3(eblocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_hydro_eos<false>, dim3(eblocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace hpac

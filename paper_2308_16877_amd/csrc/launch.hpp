@@ -96,3 +96,39 @@ hipError_t launch_mlp_grad(const MlpGradArgs &a, hipStream_t stream);
 hipError_t launch_mlp_adam(const AdamArgs &a, hipStream_t stream);
 
 }  // namespace hpac
+
+namespace hpac {
+
+// Lagrangian hydro (hydro_kernels.hip).  Hourglass-region modes:
+constexpr int kHgExact = 0, kHgTaf = 1, kHgPerfo = 2;
+
+struct HydroArgs {
+  int n;                  // elements per side
+  int64_t E, Nn, W;       // elements, nodes, waves of the element loop (one element per lane)
+  float h;                // initial edge of an element
+  float gamma, cq, cl, khg;
+  double gamma_d, cfl, growth, dvmax;
+  float *x[3], *u[3], *un[3];
+  float *mnode, *e, *p, *q, *c, *vol, *mass, *force, *fhg;
+  float *weos;
+  int32_t *rho_eos, *z_eos;
+  float *whg;
+  int32_t *rho_hg, *z_hg;
+  double *clock, *dt_partials;
+  int8_t *dec_eos, *dec_hg;
+  // technique of this step
+  int eos_h, eos_p;
+  float eos_theta;
+  int hg_h, hg_p;
+  float hg_theta;
+  int perfo_kind, perfo_param;
+  int hg_ipt;      // items per lane of the force kernel's element loop
+  int64_t hg_L;    // its logical lanes
+  int32_t step;    // timestep index (perforation offset)
+};
+int64_t hydro_lanes(int64_t E, int ipt);
+int64_t hydro_partials(int64_t E);
+hipError_t launch_hydro_init(const HydroArgs &a, double e_origin, double dt0, hipStream_t stream);
+hipError_t launch_hydro_step(const HydroArgs &a, int hg_mode, bool eos_taf, hipStream_t stream);
+
+}  // namespace hpac

@@ -60,6 +60,26 @@ class HpacError(RuntimeError):
         self.status = status
 
 
+class hpac_hydro_params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32)] + [(f, ctypes.c_double) for f in
+                                          ("side", "gamma", "cq", "cl", "khg", "cfl", "growth", "dvmax", "dt0")]
+
+
+class hpac_hydro_state(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p * 3), ("u", ctypes.c_void_p * 3), ("unew", ctypes.c_void_p * 3)] + \
+               [(f, ctypes.c_void_p) for f in ("mnode", "e", "p", "q", "c", "vol", "mass", "force", "fhg", "weos",
+                                                "rho_eos", "z_eos", "whg", "rho_hg", "z_hg", "clock",
+                                                "dt_partials")]
+
+
+class hpac_hydro_tech(ctypes.Structure):
+    _fields_ = [("eos_history", ctypes.c_int32), ("eos_prediction", ctypes.c_int32),
+                ("eos_threshold", ctypes.c_float), ("hg_history", ctypes.c_int32),
+                ("hg_prediction", ctypes.c_int32), ("hg_threshold", ctypes.c_float),
+                ("perfo_kind", ctypes.c_int32), ("perfo_param", ctypes.c_int32),
+                ("perfo_items_per_lane", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -93,6 +113,15 @@ def lib():
     for f in (L.hpac_exact, L.hpac_iact, L.hpac_taf, L.hpac_perfo, L.hpac_probe_copy, L.hpac_bs_vjp,
               L.hpac_bs_adjoint):
         f.restype = i32
+    HP, HS, HT = (ctypes.POINTER(t) for t in (hpac_hydro_params, hpac_hydro_state, hpac_hydro_tech))
+    L.hpac_hydro_waves.argtypes = [i32]
+    L.hpac_hydro_waves.restype = i64
+    L.hpac_hydro_partials.argtypes = [i32]
+    L.hpac_hydro_partials.restype = i64
+    L.hpac_hydro_init.argtypes = [HP, ctypes.c_double, HS, vp]
+    L.hpac_hydro_init.restype = i32
+    L.hpac_hydro_step.argtypes = [HP, HT, i32, HS, vp, vp, vp]
+    L.hpac_hydro_step.restype = i32
     L.hpac_num_lanes.argtypes = [i64, i32]
     L.hpac_num_lanes.restype = i64
     L.hpac_trace_entries.argtypes = [i64, i32]
@@ -322,3 +351,29 @@ def trace_fields(t):
                 writer=((t >> 16) & 0x3F).astype(np.int64), writer_valid=((t >> 22) & 1).astype(bool),
                 approx=((t >> 24) & 1).astype(bool), voted=((t >> 25) & 1).astype(bool),
                 active=((t >> 31) & 1).astype(bool))
+
+
+def hpac_hydro_waves(n):
+    return lib().hpac_hydro_waves(n)
+
+
+def hpac_hydro_partials(n):
+    return lib().hpac_hydro_partials(n)
+
+
+def _torch_stream(stream):
+    if stream is not None:
+        return stream if isinstance(stream, int) else stream.cuda_stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def hpac_hydro_init(params, e_origin, state, stream=None):
+    _call("hpac_hydro_init", lib().hpac_hydro_init(ctypes.byref(params), float(e_origin), ctypes.byref(state),
+                                                   _torch_stream(stream)))
+
+
+def hpac_hydro_step(params, tech, step, state, dec_eos=None, dec_hg=None, stream=None):
+    _call("hpac_hydro_step", lib().hpac_hydro_step(ctypes.byref(params), ctypes.byref(tech), int(step),
+                                                   ctypes.byref(state), _addr(dec_eos), _addr(dec_hg),
+                                                   _torch_stream(stream)))
