@@ -295,7 +295,9 @@ class _HyState(ctypes.Structure):
 
 class _HyTech(ctypes.Structure):
     _fields_ = [("eos_h", ctypes.c_int32), ("eos_p", ctypes.c_int32), ("eos_theta", ctypes.c_double),
+                ("eos_group", ctypes.c_int32),
                 ("hg_h", ctypes.c_int32), ("hg_p", ctypes.c_int32), ("hg_theta", ctypes.c_double),
+                ("hg_group", ctypes.c_int32),
                 ("perfo_kind", ctypes.c_int32), ("perfo_param", ctypes.c_int32), ("perfo_ipt", ctypes.c_int32),
                 ("band", ctypes.c_double)]
 
@@ -326,7 +328,8 @@ class HydroState:
         self.force, self.fhg = z(24, E), z(24, E)
         self.weos = z(max(eos_h, 1) * 4, E)
         self.whg = z(max(hg_h, 1) * 24, E)
-        self.rho_eos, self.z_eos, self.rho_hg, self.z_hg = (np.zeros(W, np.int32) for _ in range(4))
+        # decision-group state, sized for one group per element (thread level)
+        self.rho_eos, self.z_eos, self.rho_hg, self.z_hg = (np.zeros(E, np.int32) for _ in range(4))
         self.clock = z(2)
         self.eos_h, self.hg_h = eos_h, hg_h
 
@@ -373,23 +376,27 @@ def hydro_init(n, e_origin, eos_h=0, hg_h=0, **par):
 
 
 def hydro_step(s, step, eos=None, hg=None, perfo=None, band=0.0, record=False):
-    """One timestep in place.  eos / hg = (h, p, theta) for TAF on the EOS /
-    hourglass region; perfo = (kind, param, items_per_lane) for the
-    hourglass region.  With record, returns per-wave decisions and fragile
-    flags {dec_eos, dec_hg, frag_eos, frag_hg}."""
-    t = _HyTech(band=float(band))
+    """One timestep in place.  eos / hg = (h, p, theta[, group]) for TAF on
+    the EOS / hourglass region, group = 64 (wave level, the default) or 1
+    (thread level); perfo = (kind, param, items_per_lane) for the hourglass
+    region.  With record, returns per-group decisions and fragile flags
+    {dec_eos, dec_hg, frag_eos, frag_hg}."""
+    t = _HyTech(band=float(band), eos_group=GROUP_WAVE, hg_group=GROUP_WAVE)
     if eos:
         assert eos[0] <= s.eos_h
         t.eos_h, t.eos_p, t.eos_theta = int(eos[0]), int(eos[1]), float(eos[2])
+        t.eos_group = int(eos[3]) if len(eos) > 3 else GROUP_WAVE
     if hg:
         assert hg[0] <= s.hg_h
         t.hg_h, t.hg_p, t.hg_theta = int(hg[0]), int(hg[1]), float(hg[2])
+        t.hg_group = int(hg[3]) if len(hg) > 3 else GROUP_WAVE
     if perfo:
         t.perfo_kind, t.perfo_param, t.perfo_ipt = int(perfo[0]), int(perfo[1]), int(perfo[2])
     rec, out = None, None
     if record:
-        out = dict(dec_eos=np.full(s.W, -1, np.int8), dec_hg=np.full(s.W, -1, np.int8),
-                   frag_eos=np.zeros(s.W, np.uint8), frag_hg=np.zeros(s.W, np.uint8))
+        ne, nh = -(-s.E // t.eos_group), -(-s.E // t.hg_group)
+        out = dict(dec_eos=np.full(ne, -1, np.int8), dec_hg=np.full(nh, -1, np.int8),
+                   frag_eos=np.zeros(ne, np.uint8), frag_hg=np.zeros(nh, np.uint8))
         rec = _HyRec(**{k: v.ctypes.data for k, v in out.items()})
     cp, cs = s._cpar(), s._cstate()
     rc = _load().hy_step(ctypes.byref(cp), ctypes.byref(t), int(step), ctypes.byref(cs),

@@ -50,16 +50,19 @@
  * consecutive elements and the "steps" of TAF are timesteps):
  *   hourglass region: inputs the element's corner coordinates and
  *            velocities, volume, B, density and sound speed; outputs the 24
- *            hourglass corner forces.  TAF (section 3.1.3) or herded
- *            perforation (section 3.1.5) with the grid-stride mapping of the
- *            element loop and offset = timestep.  An approximated or
- *            skipped element reuses its last computed hourglass forces.
+ *            hourglass corner forces, which the element adds to its corner
+ *            forces.  TAF (section 3.1.3): an approximated element adds its
+ *            last computed hourglass forces.  Herded perforation (section
+ *            3.1.5) with the grid-stride mapping of the element loop and
+ *            offset = timestep: a skipped iteration computes and adds
+ *            nothing, so the element has no hourglass force that step.
  *   EOS region: inputs e, c, mass, the corner forces and the corner
  *            velocities before and after the step and the new corner
  *            positions; outputs e, p, q, c.  TAF: an approximated element
  *            keeps its previous e, p, q, c.
- * TAF state (windows, per-wave countdown and push count) persists across
- * timesteps in the state arrays.
+ * TAF decisions are taken per wave (majority of its lanes) or per element
+ * (thread level, section 3.1.2); the state (windows, a countdown and a push
+ * count per decision group) persists across timesteps in the state arrays.
  */
 #include <math.h>
 #include <stdint.h>
@@ -90,7 +93,7 @@ typedef struct {
   double *force;            /* corner forces [(corner*3 + dim) * E + z] */
   double *fhg;              /* last computed hourglass forces, same layout */
   double *weos;             /* EOS TAF window [(slot*4 + o) * E + z] */
-  int32_t *rho_eos, *z_eos; /* per wave: countdown, accurate pushes */
+  int32_t *rho_eos, *z_eos; /* per decision group: countdown, accurate pushes */
   double *whg;              /* hourglass TAF window [(slot*24 + o) * E + z] */
   int32_t *rho_hg, *z_hg;
   double *clock;            /* [0] time, [1] last time step */
@@ -99,8 +102,10 @@ typedef struct {
 typedef struct {
   int32_t eos_h, eos_p;  /* EOS TAF: history and prediction sizes (h = 0: exact) */
   double eos_theta;
+  int32_t eos_group;     /* lanes per decision: 1 (thread level) or 64 (wave level) */
   int32_t hg_h, hg_p;    /* hourglass TAF (h = 0: none) */
   double hg_theta;
+  int32_t hg_group;
   int32_t perfo_kind;    /* hourglass perforation: 0 small, 1 large, 2 ini, 3 fini */
   int32_t perfo_param;   /* M for small/large, percent for ini/fini; 0 = none */
   int32_t perfo_ipt;     /* items per lane of the perforated element loop */
@@ -108,8 +113,8 @@ typedef struct {
 } hy_tech;
 
 typedef struct {
-  int8_t *dec_eos, *dec_hg;     /* per wave: -1 no vote, 0 accurate, 1 approximate; NULL = none */
-  uint8_t *frag_eos, *frag_hg;  /* per wave: the vote flips within the band */
+  int8_t *dec_eos, *dec_hg;     /* per decision group: -1 none, 0 accurate, 1 approximate; NULL = none */
+  uint8_t *frag_eos, *frag_hg;  /* per decision group: the vote flips within the band */
 } hy_rec;
 
 static inline int64_t hy_elems(const hy_par *P) { return (int64_t)P->n * P->n * P->n; }
@@ -232,10 +237,10 @@ int hy_init(const hy_par *P, double e_origin, hy_state *S) {
     }
     S->mnode[v] = M;
   }
-  const int64_t W = (E + HY_WAVE - 1) / HY_WAVE;
-  for (int64_t w = 0; w < W; ++w) {
-    if (S->rho_eos) S->rho_eos[w] = 0, S->z_eos[w] = 0;
-    if (S->rho_hg) S->rho_hg[w] = 0, S->z_hg[w] = 0;
+  /* decision-group state: sized for the finest grouping (one per element) */
+  for (int64_t g = 0; g < E; ++g) {
+    if (S->rho_eos) S->rho_eos[g] = 0, S->z_eos[g] = 0;
+    if (S->rho_hg) S->rho_hg[g] = 0, S->z_hg[g] = 0;
   }
   S->clock[0] = 0.0;
   S->clock[1] = P->dt0;
@@ -305,8 +310,10 @@ static void hy_gather(const hy_par *P, const hy_state *S, int64_t z, double xc[8
 }
 
 /* Force phase for one element: V, B, pressure and hourglass corner forces.
- * hg: 1 compute the hourglass forces (and remember them), 0 reuse the
- * remembered ones.  Returns the element's time-step bound. */
+ * hg: HY_HG_COMPUTE compute the hourglass forces (and remember them),
+ * HY_HG_REUSE add the remembered ones, HY_HG_NONE add none.  Returns the
+ * element's time-step bound. */
+enum { HY_HG_NONE = 0, HY_HG_COMPUTE = 1, HY_HG_REUSE = 2 };
 static double hy_force_elem(const hy_par *P, hy_state *S, int64_t z, int hg) {
   const int64_t E = hy_elems(P);
   double xc[8][3], uc[8][3], B[8][3], f[8][3];
@@ -314,14 +321,18 @@ static double hy_force_elem(const hy_par *P, hy_state *S, int64_t z, int hg) {
   const double V = hy_volume(xc, B);
   S->vol[z] = V;
   const double rho = S->mass[z] / V;
-  if (hg) {
+  if (hg == HY_HG_COMPUTE) {
     hy_hourglass(xc, uc, B, V, rho, S->c[z], P->khg, f);
+    if (S->fhg)
+      for (int k = 0; k < 8; ++k)
+        for (int d = 0; d < 3; ++d) S->fhg[(k * 3 + d) * E + z] = f[k][d];
+  } else {
     for (int k = 0; k < 8; ++k)
-      for (int d = 0; d < 3; ++d) S->fhg[(k * 3 + d) * E + z] = f[k][d];
+      for (int d = 0; d < 3; ++d) f[k][d] = hg == HY_HG_REUSE ? S->fhg[(k * 3 + d) * E + z] : 0.0;
   }
   const double pq = S->p[z] + S->q[z];
   for (int k = 0; k < 8; ++k)
-    for (int d = 0; d < 3; ++d) S->force[(k * 3 + d) * E + z] = pq * B[k][d] + S->fhg[(k * 3 + d) * E + z];
+    for (int d = 0; d < 3; ++d) S->force[(k * 3 + d) * E + z] = pq * B[k][d] + f[k][d];
   const double ceff2 = P->gamma * fmax(pq, 0.0) / rho;
   double bound = ceff2 > 0.0 ? P->cfl * cbrt(V) / sqrt(ceff2) : INFINITY;
   /* relative volume change per step at most dvmax: dV/dt = sum B . u */
@@ -361,18 +372,22 @@ static void hy_eos_elem(const hy_par *P, const hy_state *S, int64_t z, double dt
 /* One timestep.  step = the timestep index (the perforation offset). */
 int hy_step(const hy_par *P, const hy_tech *T, int32_t step, hy_state *S, hy_rec *R) {
   const int64_t n = P->n, m = n + 1, E = hy_elems(P), Nn = hy_nodes(P);
-  const int64_t W = (E + HY_WAVE - 1) / HY_WAVE;
   if ((T->eos_h && (T->eos_h > HY_MAX_H || T->eos_p < 1)) || (T->hg_h && (T->hg_h > HY_MAX_H || T->hg_p < 1)))
     return -1;
+  if ((T->eos_group != 1 && T->eos_group != HY_WAVE) || (T->hg_group != 1 && T->hg_group != HY_WAVE)) return -1;
+  const int64_t GE = T->eos_group, GH = T->hg_group;
+  const int64_t NGE = (E + GE - 1) / GE, NGH = (E + GH - 1) / GH;
   if (T->hg_h && T->perfo_param) return -1;
   if (T->perfo_param && T->perfo_ipt < 1) return -1;
   if (T->perfo_kind < 0 || T->perfo_kind > 3) return -1;
   if (R) {
-    for (int64_t w = 0; w < W; ++w) {
-      if (R->dec_eos) R->dec_eos[w] = -1;
-      if (R->dec_hg) R->dec_hg[w] = -1;
-      if (R->frag_eos) R->frag_eos[w] = 0;
-      if (R->frag_hg) R->frag_hg[w] = 0;
+    for (int64_t g = 0; g < NGE; ++g) {
+      if (R->dec_eos) R->dec_eos[g] = -1;
+      if (R->frag_eos) R->frag_eos[g] = 0;
+    }
+    for (int64_t g = 0; g < NGH; ++g) {
+      if (R->dec_hg) R->dec_hg[g] = -1;
+      if (R->frag_hg) R->frag_hg[g] = 0;
     }
   }
 
@@ -386,28 +401,28 @@ int hy_step(const hy_par *P, const hy_tech *T, int32_t step, hy_state *S, hy_rec
       for (int32_t k = 0; k < T->perfo_ipt; ++k) {
         const int64_t z = l + (int64_t)k * L;
         if (z >= E) continue;
-        const double b = hy_force_elem(P, S, z, !hy_perfo_skip(T, z, E, k, step));
+        const double b = hy_force_elem(P, S, z, hy_perfo_skip(T, z, E, k, step) ? HY_HG_NONE : HY_HG_COMPUTE);
         dtmin = fmin(dtmin, b);
       }
   } else {
 #pragma omp parallel for schedule(static) reduction(min : dtmin)
-    for (int64_t w = 0; w < W; ++w) {
-      const int64_t z0 = w * HY_WAVE, z1 = z0 + HY_WAVE < E ? z0 + HY_WAVE : E;
+    for (int64_t g = 0; g < NGH; ++g) {
+      const int64_t z0 = g * GH, z1 = z0 + GH < E ? z0 + GH : E;
       const int act = (int)(z1 - z0);
-      if (T->hg_h && S->rho_hg[w] > 0) {
-        for (int64_t z = z0; z < z1; ++z) dtmin = fmin(dtmin, hy_force_elem(P, S, z, 0));
-        S->rho_hg[w]--;
-        if (R && R->dec_hg) R->dec_hg[w] = 1;
+      if (T->hg_h && S->rho_hg[g] > 0) {
+        for (int64_t z = z0; z < z1; ++z) dtmin = fmin(dtmin, hy_force_elem(P, S, z, HY_HG_REUSE));
+        S->rho_hg[g]--;
+        if (R && R->dec_hg) R->dec_hg[g] = 1;
         continue;
       }
       int yes = 0, voted = 0, near_yes = 0, near_no = 0;
       for (int64_t z = z0; z < z1; ++z) {
-        dtmin = fmin(dtmin, hy_force_elem(P, S, z, 1));
+        dtmin = fmin(dtmin, hy_force_elem(P, S, z, HY_HG_COMPUTE));
         if (!T->hg_h) continue;
         double y[24];
         for (int o = 0; o < 24; ++o) y[o] = S->fhg[o * E + z];
         int near;
-        const int crit = hy_taf_push(S->whg, E, z, 24, T->hg_h, S->z_hg[w], y, T->hg_theta, T->band, &near);
+        const int crit = hy_taf_push(S->whg, E, z, 24, T->hg_h, S->z_hg[g], y, T->hg_theta, T->band, &near);
         if (crit >= 0) {
           voted = 1;
           yes += crit;
@@ -415,11 +430,11 @@ int hy_step(const hy_par *P, const hy_tech *T, int32_t step, hy_state *S, hy_rec
         }
       }
       if (!T->hg_h) continue;
-      S->z_hg[w]++;
-      if (R && R->dec_hg) R->dec_hg[w] = 0;
-      if (voted && hy_majority(yes, act)) S->rho_hg[w] = T->hg_p;
+      S->z_hg[g]++;
+      if (R && R->dec_hg) R->dec_hg[g] = 0;
+      if (voted && hy_majority(yes, act)) S->rho_hg[g] = T->hg_p;
       if (voted && R && R->frag_hg)
-        R->frag_hg[w] = hy_majority(yes - near_yes, act) != hy_majority(yes + near_no, act);
+        R->frag_hg[g] = hy_majority(yes - near_yes, act) != hy_majority(yes + near_no, act);
     }
   }
 
@@ -448,12 +463,12 @@ int hy_step(const hy_par *P, const hy_tech *T, int32_t step, hy_state *S, hy_rec
 
   /* 4. EOS region per element (TAF or exact) */
 #pragma omp parallel for schedule(static)
-  for (int64_t w = 0; w < W; ++w) {
-    const int64_t z0 = w * HY_WAVE, z1 = z0 + HY_WAVE < E ? z0 + HY_WAVE : E;
+  for (int64_t g = 0; g < NGE; ++g) {
+    const int64_t z0 = g * GE, z1 = z0 + GE < E ? z0 + GE : E;
     const int act = (int)(z1 - z0);
-    if (T->eos_h && S->rho_eos[w] > 0) {
-      S->rho_eos[w]--;
-      if (R && R->dec_eos) R->dec_eos[w] = 1;
+    if (T->eos_h && S->rho_eos[g] > 0) {
+      S->rho_eos[g]--;
+      if (R && R->dec_eos) R->dec_eos[g] = 1;
       continue;
     }
     int yes = 0, voted = 0, near_yes = 0, near_no = 0;
@@ -466,7 +481,7 @@ int hy_step(const hy_par *P, const hy_tech *T, int32_t step, hy_state *S, hy_rec
       S->c[z] = y[3];
       if (!T->eos_h) continue;
       int near;
-      const int crit = hy_taf_push(S->weos, E, z, 4, T->eos_h, S->z_eos[w], y, T->eos_theta, T->band, &near);
+      const int crit = hy_taf_push(S->weos, E, z, 4, T->eos_h, S->z_eos[g], y, T->eos_theta, T->band, &near);
       if (crit >= 0) {
         voted = 1;
         yes += crit;
@@ -474,11 +489,11 @@ int hy_step(const hy_par *P, const hy_tech *T, int32_t step, hy_state *S, hy_rec
       }
     }
     if (!T->eos_h) continue;
-    S->z_eos[w]++;
-    if (R && R->dec_eos) R->dec_eos[w] = 0;
-    if (voted && hy_majority(yes, act)) S->rho_eos[w] = T->eos_p;
+    S->z_eos[g]++;
+    if (R && R->dec_eos) R->dec_eos[g] = 0;
+    if (voted && hy_majority(yes, act)) S->rho_eos[g] = T->eos_p;
     if (voted && R && R->frag_eos)
-      R->frag_eos[w] = hy_majority(yes - near_yes, act) != hy_majority(yes + near_no, act);
+      R->frag_eos[g] = hy_majority(yes - near_yes, act) != hy_majority(yes + near_no, act);
   }
 
   /* 5. velocities and clock */

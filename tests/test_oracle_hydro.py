@@ -228,16 +228,19 @@ def test_approximated_elements_keep_their_outputs():
 
 
 @pytest.mark.parametrize("kind,param,ipt", [(0, 4, 8), (1, 3, 6), (2, 20, 1), (3, 20, 1)])
-def test_perforated_elements_keep_their_hourglass_forces(kind, param, ipt):
+def test_perforated_elements_add_no_hourglass_force(kind, param, ipt):
+    """A skipped iteration of the hourglass loop computes and adds nothing:
+    the element's corner forces are its pressure forces (p + q) B alone; a
+    computed one adds the hourglass force of its corners."""
     n = 8
     E = n ** 3
     s = oracle.hydro_init(n, (1.0 / 8) * n ** 3)
     L = oracle.num_lanes(E, ipt)
     z = np.arange(E)
     k_of = z // L
-    computed_nonzero = False
-    for step in range(40):
-        before = s.fhg.copy()
+    checked_hg = 0
+    for step in range(30):
+        before = s.copy()
         oracle.hydro_step(s, step, perfo=(kind, param, ipt))
         if kind == 0:
             skipped = (k_of + step) % param == param - 1
@@ -247,6 +250,43 @@ def test_perforated_elements_keep_their_hourglass_forces(kind, param, ipt):
             skipped = z < param * E // 100
         else:
             skipped = z >= E - param * E // 100
-        assert np.array_equal(s.fhg[:, skipped], before[:, skipped])
-        computed_nonzero |= bool(np.any((np.abs(s.fhg).sum(axis=0) > 0) & ~skipped))
-    assert computed_nonzero
+        if step % 6:
+            continue
+        for e in range(0, E, 7):
+            i, j, k = e % n, (e // n) % n, e // (n * n)
+            nodes = [(i + (c & 1)) + (n + 1) * ((j + ((c >> 1) & 1)) + (n + 1) * (k + ((c >> 2) & 1)))
+                     for c in range(8)]
+            xc = before.x[:, nodes].T
+            uc = before.u[:, nodes].T
+            V, B = oracle.hex_volume(xc)
+            f = s.force[:, e].reshape(8, 3)
+            fp = (before.p[e] + before.q[e]) * B
+            if skipped[e]:
+                assert np.array_equal(f, fp)
+            else:
+                fh = oracle.hex_hourglass(xc, uc, before.mass[e] / V, before.c[e], s.par["khg"])
+                assert np.array_equal(f, fp + fh)
+                checked_hg += int(np.any(fh != 0))
+    assert checked_hg > 0
+
+
+def test_thread_level_taf_decides_per_element():
+    """Thread level (section 3.1.2): each element keeps its own countdown, so
+    within one wave some elements compute while others reuse; with a
+    threshold no finite RSD reaches every element follows the h, then
+    (p approximate + 1 accurate) pattern; threshold 0 is exact."""
+    h, p = 3, 2
+    s, recs = run(8, 20, eos=(h, p, 1e300, 1))
+    dec = np.stack([r["dec_eos"] for r in recs])  # (steps, elements)
+    assert dec.shape[1] == 8 ** 3
+    expect = [0] * h + ([1] * p + [0]) * 10
+    assert all(list(dec[:, z]) == expect[:20] for z in range(dec.shape[1]))
+    s, recs = run(10, 60, eos=(4, 4, 0.01, 1), hg=(4, 4, 0.05, 1))
+    mixed = 0
+    for r in recs:
+        d = r["dec_eos"][:(len(r["dec_eos"]) // 64) * 64].reshape(-1, 64)
+        mixed += int(np.sum((d == 1).any(axis=1) & (d == 0).any(axis=1)))
+    assert mixed > 0
+    ref, _ = run(8, 40)
+    s, _ = run(8, 40, eos=(4, 4, 0.0, 1), hg=(2, 3, 0.0, 1))
+    assert same_state(s, ref)
