@@ -255,16 +255,19 @@ hpac_status hpac_mlp_adam(const float *grad_partials, int64_t blocks, float *par
  * Two per-element regions take the paper's techniques with one element per
  * lane (a wave is 64 consecutive elements, a TAF step is a timestep, TAF
  * state persists in the caller's buffers between calls):
- *  - hourglass region (24 corner forces): TAF (history 1..8) or herded
- *    perforation (section 3.1.5) of the element loop at
- *    perfo_items_per_lane, offset = timestep; approximated or skipped
- *    elements reuse their last computed forces (fhg);
+ *  - hourglass region (24 corner forces, added to the element's corner
+ *    forces): TAF (history 1..8; an approximated element adds its last
+ *    accurate forces, fhg) or herded perforation (section 3.1.5) of the
+ *    element loop at perfo_items_per_lane, offset = timestep (a skipped
+ *    iteration adds nothing);
  *  - EOS region (e, p, q, c): TAF; approximated elements keep their values.
+ * TAF decides per wave (majority of its 64 elements) or per element (thread
+ * level), the two finest levels of section 3.1.2.
  * Layouts: element fields n^3 floats, element z = i + n (j + n k); node
  * fields (n+1)^3 floats, node i + (n+1) (j + (n+1) k); force and fhg are
  * [(corner * 3 + dim) * n^3 + z] with corner a + 2b + 4c for node
  * (i+a, j+b, k+c); windows are [(slot * outputs + o) * n^3 + z];
- * per-wave ints have hpac_hydro_waves(n) entries.  All device memory, owned
+ * per-group ints have hpac_hydro_groups(n, level) entries.  All device memory, owned
  * by the caller.  Calls are asynchronous on `stream`; the time step stays
  * on the device (clock), so a step never waits for the host.
  * ------------------------------------------------------------------------ */
@@ -286,9 +289,9 @@ typedef struct hpac_hydro_state {
   float *e, *p, *q, *c;         /* element specific energy, pressure, viscosity, sound speed */
   float *vol, *mass;            /* element volume at the last force evaluation, mass */
   float *force;                 /* corner forces, 24 n^3 */
-  float *fhg;                   /* last hourglass forces, 24 n^3 (needed when approximated) */
+  float *fhg;                   /* last hourglass forces, 24 n^3 (hourglass TAF only) */
   float *weos;                  /* EOS window, eos_history * 4 n^3 (EOS TAF only) */
-  int32_t *rho_eos, *z_eos;     /* per wave: countdown, pushes (EOS TAF only) */
+  int32_t *rho_eos, *z_eos;     /* per decision group: countdown, pushes (EOS TAF only) */
   float *whg;                   /* hourglass window, hg_history * 24 n^3 (hourglass TAF only) */
   int32_t *rho_hg, *z_hg;
   double *clock;                /* [0] time, [1] last time step */
@@ -298,26 +301,33 @@ typedef struct hpac_hydro_state {
 typedef struct hpac_hydro_tech {
   int32_t eos_history, eos_prediction; /* EOS TAF; history 0 = exact */
   float eos_threshold;
+  int32_t eos_level;                   /* HPAC_LEVEL_WAVE or HPAC_LEVEL_THREAD */
   int32_t hg_history, hg_prediction;   /* hourglass TAF; history 0 = none */
   float hg_threshold;
+  int32_t hg_level;
   int32_t perfo_kind;                  /* hourglass perforation, HPAC_PERFO_* */
   int32_t perfo_param;                 /* 0 = none */
   int32_t perfo_items_per_lane;        /* 1..64 */
 } hpac_hydro_tech;
 
-/* Entries of the per-wave arrays and of dt_partials; -1 if n is invalid. */
+/* Waves of the element loop, TAF decision groups at `level` (waves, or
+ * elements at thread level: the size of rho_*, z_* and of dec_*), and
+ * entries of dt_partials; -1 if an argument is invalid. */
 int64_t hpac_hydro_waves(int32_t n);
+int64_t hpac_hydro_groups(int32_t n, int32_t level);
 int64_t hpac_hydro_partials(int32_t n);
 
-/* Initial state (every non-NULL field of *state is written; the TAF counters
- * are zeroed, fhg is zeroed if given). */
+/* Initial state (every non-NULL field of *state is written; fhg is zeroed if
+ * given, and rho_* / z_* are zeroed over hpac_hydro_groups(n, THREAD)
+ * entries, so they must have that many when given). */
 hpac_status hpac_hydro_init(const hpac_hydro_params *params, double e_origin, const hpac_hydro_state *state,
                             void *stream);
 
 /* One timestep with index `step` (the perforation offset).  On return, in
  * stream order, the velocities after the step are in state->unew: swap u
  * and unew before the next call.  dec_eos / dec_hg (optional, device int8
- * per wave): 0 the wave computed the region this step, 1 it approximated.
+ * per decision group): 0 the group computed the region this step, 1 it
+ * approximated.
  * Fields a technique needs must be non-NULL (HPAC_EINVAL otherwise). */
 hpac_status hpac_hydro_step(const hpac_hydro_params *params, const hpac_hydro_tech *tech, int32_t step,
                             const hpac_hydro_state *state, int8_t *dec_eos, int8_t *dec_hg, void *stream);

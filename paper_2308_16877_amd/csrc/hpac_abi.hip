@@ -393,6 +393,13 @@ int64_t hpac_hydro_waves(int32_t n) {
   return hpac::hydro_lanes((int64_t)n * n * n, 1) / 64;
 }
 
+int64_t hpac_hydro_groups(int32_t n, int32_t level) {
+  if (n < 1 || n > 1000) return -1;
+  if (level == HPAC_LEVEL_THREAD) return (int64_t)n * n * n;
+  if (level == HPAC_LEVEL_WAVE) return hpac::hydro_lanes((int64_t)n * n * n, 1) / 64;
+  return -1;
+}
+
 int64_t hpac_hydro_partials(int32_t n) {
   if (n < 1 || n > 1000) return -1;
   return hpac::hydro_partials((int64_t)n * n * n);
@@ -428,6 +435,9 @@ hpac_status hpac_hydro_step(const hpac_hydro_params *params, const hpac_hydro_te
     return fail(HPAC_EINVAL, "%s: history sizes must be in [0, 8]", fn);
   if ((T.eos_history && T.eos_prediction < 1) || (T.hg_history && T.hg_prediction < 1))
     return fail(HPAC_EINVAL, "%s: prediction sizes must be >= 1", fn);
+  if ((T.eos_history && T.eos_level != HPAC_LEVEL_WAVE && T.eos_level != HPAC_LEVEL_THREAD) ||
+      (T.hg_history && T.hg_level != HPAC_LEVEL_WAVE && T.hg_level != HPAC_LEVEL_THREAD))
+    return fail(HPAC_EINVAL, "%s: hydro TAF levels are HPAC_LEVEL_WAVE or HPAC_LEVEL_THREAD", fn);
   if (!(T.eos_threshold >= 0.0f) || !isfinite(T.eos_threshold) || !(T.hg_threshold >= 0.0f) ||
       !isfinite(T.hg_threshold))
     return fail(HPAC_EINVAL, "%s: thresholds must be finite and >= 0", fn);
@@ -442,8 +452,7 @@ hpac_status hpac_hydro_step(const hpac_hydro_params *params, const hpac_hydro_te
     return fail(HPAC_EINVAL, "%s: EOS TAF needs weos, rho_eos and z_eos", fn);
   if (T.hg_history && (!aligned4(state->whg) || !aligned4(state->rho_hg) || !aligned4(state->z_hg)))
     return fail(HPAC_EINVAL, "%s: hourglass TAF needs whg, rho_hg and z_hg", fn);
-  if ((T.hg_history || T.perfo_param) && !aligned4(state->fhg))
-    return fail(HPAC_EINVAL, "%s: an approximated hourglass region needs fhg", fn);
+  if (T.hg_history && !aligned4(state->fhg)) return fail(HPAC_EINVAL, "%s: hourglass TAF needs fhg", fn);
   hpac::HydroArgs a = hydro_args(params, state);
   a.step = step;
   a.dec_eos = T.eos_history ? dec_eos : nullptr;
@@ -458,13 +467,15 @@ hpac_status hpac_hydro_step(const hpac_hydro_params *params, const hpac_hydro_te
   a.perfo_param = T.perfo_param;
   int mode = hpac::kHgExact;
   if (T.hg_history) {
-    mode = hpac::kHgTaf;
+    mode = T.hg_level == HPAC_LEVEL_THREAD ? hpac::kHgTafThread : hpac::kHgTafWave;
   } else if (T.perfo_param) {
     mode = hpac::kHgPerfo;
     a.hg_ipt = T.perfo_items_per_lane;
     a.hg_L = hpac::hydro_lanes(a.E, a.hg_ipt);
   }
-  return hip_status(fn, hpac::launch_hydro_step(a, mode, T.eos_history > 0, (hipStream_t)stream));
+  int eos_mode = hpac::kEosExact;
+  if (T.eos_history) eos_mode = T.eos_level == HPAC_LEVEL_THREAD ? hpac::kEosTafThread : hpac::kEosTafWave;
+  return hip_status(fn, hpac::launch_hydro_step(a, mode, eos_mode, (hipStream_t)stream));
 }
 
 hpac_status hpac_probe_copy(const void *src, void *dst, int64_t bytes, void *stream) {

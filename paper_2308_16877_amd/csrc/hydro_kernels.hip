@@ -23,11 +23,12 @@
 //                  pressure, von Neumann-Richtmyer viscosity from the
 //                  volume rate sum B(x') . (u + u')/2, sound speed.
 // One element per lane, so a wave is 64 consecutive elements and a TAF
-// "step" is a timestep: windows live in HBM, the countdown and push count of
-// each wave in one int each, read once per wave and written by its first
-// lane.  An approximate wave-step of the EOS region reads only its
-// countdown; one of the hourglass region reads the last hourglass forces
-// instead of computing them.
+// "step" is a timestep: windows live in HBM.  At wave level the countdown
+// and push count of each wave are one int each, read by the whole wave and
+// written by its first lane; at thread level every element has its own.
+// An approximate EOS step reads only the countdown; an approximate
+// hourglass step adds the last accurate hourglass forces instead of
+// computing them.  A perforated hourglass iteration adds nothing.
 #include "launch.hpp"
 #include "wave.hpp"
 
@@ -286,15 +287,16 @@ __global__ void __launch_bounds__(256) k_hydro_init_node(HydroArgs a) {
   }
 }
 
-__global__ void __launch_bounds__(256) k_hydro_init_waves(HydroArgs a, double dt0) {
-  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (w == 0) {
+// TAF decision-group state, over one entry per element (the largest grouping)
+__global__ void __launch_bounds__(256) k_hydro_init_groups(HydroArgs a, double dt0) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g == 0) {
     a.clock[0] = 0.0;
     a.clock[1] = dt0;
   }
-  if (w >= a.W) return;
-  if (a.rho_eos) a.rho_eos[w] = 0, a.z_eos[w] = 0;
-  if (a.rho_hg) a.rho_hg[w] = 0, a.z_hg[w] = 0;
+  if (g >= a.E) return;
+  if (a.rho_eos) a.rho_eos[g] = 0, a.z_eos[g] = 0;
+  if (a.rho_hg) a.rho_hg[g] = 0, a.z_hg[g] = 0;
 }
 
 // ------------------------------------------------------------------ force
@@ -311,6 +313,7 @@ __global__ void __launch_bounds__(256) k_hydro_force(HydroArgs a) {
     const int64_t z = l + (int64_t)k * a.hg_L;
     const bool active = z < E;
     const int64_t w = l >> 6;  // TAF: one element per lane
+    constexpr bool kTaf = HG == kHgTafWave || HG == kHgTafThread;
     bool compute_hg = true;
     int rho = 0, pushes = 0;
     if (HG == kHgPerfo) {
@@ -324,9 +327,14 @@ __global__ void __launch_bounds__(256) k_hydro_force(HydroArgs a) {
         }
       }
     }
-    if (HG == kHgTaf && w < a.W) {
+    if (HG == kHgTafWave && w < a.W) {
       rho = a.rho_hg[w];
       pushes = a.z_hg[w];
+      compute_hg = rho <= 0;
+    }
+    if (HG == kHgTafThread && active) {
+      rho = a.rho_hg[z];
+      pushes = a.z_hg[z];
       compute_hg = rho <= 0;
     }
     bool crit = false, voted = false;
@@ -340,12 +348,15 @@ __global__ void __launch_bounds__(256) k_hydro_force(HydroArgs a) {
       const float rho_e = a.mass[z] / V;
       if (compute_hg) {
         hourglass(x, u, B, V, rho_e, a.c[z], a.khg, f);
-        if (HG != kHgExact)
+        if (kTaf)
 #pragma unroll
           for (int o = 0; o < 24; ++o) a.fhg[o * E + z] = f[o / 3][o % 3];
-      } else {
+      } else if (kTaf) {  // TAF's approximate path: the last accurate forces
 #pragma unroll
         for (int o = 0; o < 24; ++o) f[o / 3][o % 3] = a.fhg[o * E + z];
+      } else {  // a perforated iteration adds no hourglass force
+#pragma unroll
+        for (int o = 0; o < 24; ++o) f[o / 3][o % 3] = 0.0f;
       }
       const float pq = a.p[z] + a.q[z];
       float vdot = 0.0f;
@@ -362,7 +373,7 @@ __global__ void __launch_bounds__(256) k_hydro_force(HydroArgs a) {
       double b = ceff2 > 0.0 ? a.cfl * cbrt(Vd) / sqrt(ceff2) : INFINITY;
       if (vdot != 0.0f) b = fmin(b, a.dvmax * Vd / fabs((double)vdot));
       bound = fmin(bound, b);
-      if (HG == kHgTaf && compute_hg) {
+      if (kTaf && compute_hg) {
         const int slot = pushes % a.hg_h;
         float y[24];
 #pragma unroll
@@ -377,7 +388,16 @@ __global__ void __launch_bounds__(256) k_hydro_force(HydroArgs a) {
         }
       }
     }
-    if (HG == kHgTaf && w < a.W) {
+    if (HG == kHgTafThread && active) {
+      if (!compute_hg) {
+        a.rho_hg[z] = rho - 1;
+      } else {
+        a.z_hg[z] = pushes + 1;
+        if (crit) a.rho_hg[z] = a.hg_p;
+      }
+      if (a.dec_hg) a.dec_hg[z] = compute_hg ? 0 : 1;
+    }
+    if (HG == kHgTafWave && w < a.W) {
       const uint64_t amask = ballot(active);
       const uint64_t vmask = ballot(crit);
       const bool any_vote = ballot(voted) != 0;
@@ -442,8 +462,9 @@ __global__ void __launch_bounds__(256) k_hydro_node(HydroArgs a) {
 
 // ------------------------------------------------------------------ EOS
 
-template <bool kTaf>
+template <int EOS>
 __global__ void __launch_bounds__(256) k_hydro_eos(HydroArgs a) {
+  constexpr bool kTaf = EOS != kEosExact;
   const int n = a.n;
   const int64_t E = a.E;
   const int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -452,7 +473,7 @@ __global__ void __launch_bounds__(256) k_hydro_eos(HydroArgs a) {
   const int lane = lane_id();
   const bool active = z < E;
   int pushes = 0;
-  if (kTaf) {
+  if (EOS == kEosTafWave) {
     const int rho = a.rho_eos[w];
     if (rho > 0) {
       if (lane == 0) {
@@ -462,6 +483,16 @@ __global__ void __launch_bounds__(256) k_hydro_eos(HydroArgs a) {
       return;
     }
     pushes = a.z_eos[w];
+  }
+  if (EOS == kEosTafThread) {
+    if (!active) return;
+    const int rho = a.rho_eos[z];
+    if (rho > 0) {
+      a.rho_eos[z] = rho - 1;
+      if (a.dec_eos) a.dec_eos[z] = 1;
+      return;
+    }
+    pushes = a.z_eos[z];
   }
   bool crit = false, voted = false;
   if (active) {
@@ -508,7 +539,12 @@ __global__ void __launch_bounds__(256) k_hydro_eos(HydroArgs a) {
       }
     }
   }
-  if (kTaf) {
+  if (EOS == kEosTafThread) {
+    a.z_eos[z] = pushes + 1;
+    if (crit) a.rho_eos[z] = a.eos_p;
+    if (a.dec_eos) a.dec_eos[z] = 0;
+  }
+  if (EOS == kEosTafWave) {
     const uint64_t amask = ballot(active);
     const uint64_t vmask = ballot(crit);
     const bool any_vote = ballot(voted) != 0;
@@ -529,24 +565,26 @@ int64_t hydro_partials(int64_t E) { return (hydro_lanes(E, 1) + 255) / 256; }
 hipError_t launch_hydro_init(const HydroArgs &a, double e_origin, double dt0, hipStream_t s) {
   hipLaunchKernelGGL(k_hydro_init_elem, dim3((unsigned)((a.E + 255) / 256)), dim3(256), 0, s, a, e_origin);
   hipLaunchKernelGGL(k_hydro_init_node, dim3((unsigned)((a.Nn + 255) / 256)), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_hydro_init_waves, dim3((unsigned)((a.W + 255) / 256)), dim3(256), 0, s, a, dt0);
+  hipLaunchKernelGGL(k_hydro_init_groups, dim3((unsigned)((a.E + 255) / 256)), dim3(256), 0, s, a, dt0);
   return hipGetLastError();
 }
 
-hipError_t launch_hydro_step(const HydroArgs &a, int hg_mode, bool eos_taf, hipStream_t s) {
+hipError_t launch_hydro_step(const HydroArgs &a, int hg_mode, int eos_mode, hipStream_t s) {
   const unsigned fblocks = (unsigned)((a.hg_L + 255) / 256);
   switch (hg_mode) {
     case kHgExact: hipLaunchKernelGGL(k_hydro_force<kHgExact>, dim3(fblocks), dim3(256), 0, s, a); break;
-    case kHgTaf: hipLaunchKernelGGL(k_hydro_force<kHgTaf>, dim3(fblocks), dim3(256), 0, s, a); break;
+    case kHgTafWave: hipLaunchKernelGGL(k_hydro_force<kHgTafWave>, dim3(fblocks), dim3(256), 0, s, a); break;
+    case kHgTafThread: hipLaunchKernelGGL(k_hydro_force<kHgTafThread>, dim3(fblocks), dim3(256), 0, s, a); break;
     default: hipLaunchKernelGGL(k_hydro_force<kHgPerfo>, dim3(fblocks), dim3(256), 0, s, a); break;
   }
   hipLaunchKernelGGL(k_hydro_dt, dim3(1), dim3(256), 0, s, a, (int64_t)fblocks);
   hipLaunchKernelGGL(k_hydro_node, dim3((unsigned)((a.Nn + 255) / 256)), dim3(256), 0, s, a);
   const unsigned eblocks = (unsigned)((hydro_lanes(a.E, 1) + 255) / 256);
-  if (eos_taf)
-    hipLaunchKernelGGL(k_hydro_eos<true>, dim3(eblocks), dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_hydro_eos<false>, dim3(eblocks), dim3(256), 0, s, a);
+  switch (eos_mode) {
+    case kEosExact: hipLaunchKernelGGL(k_hydro_eos<kEosExact>, dim3(eblocks), dim3(256), 0, s, a); break;
+    case kEosTafWave: hipLaunchKernelGGL(k_hydro_eos<kEosTafWave>, dim3(eblocks), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL(k_hydro_eos<kEosTafThread>, dim3(eblocks), dim3(256), 0, s, a); break;
+  }
   return hipGetLastError();
 }
 

@@ -99,8 +99,9 @@ hipError_t launch_mlp_adam(const AdamArgs &a, hipStream_t stream);
 
 namespace hpac {
 
-// Lagrangian hydro (hydro_kernels.hip).  Hourglass-region modes:
-constexpr int kHgExact = 0, kHgTaf = 1, kHgPerfo = 2;
+// Lagrangian hydro (hydro_kernels.hip).  Region modes:
+constexpr int kHgExact = 0, kHgTafWave = 1, kHgTafThread = 2, kHgPerfo = 3;
+constexpr int kEosExact = 0, kEosTafWave = 1, kEosTafThread = 2;
 
 struct HydroArgs {
   int n;                  // elements per side
@@ -129,6 +130,6 @@ struct HydroArgs {
 int64_t hydro_lanes(int64_t E, int ipt);
 int64_t hydro_partials(int64_t E);
 hipError_t launch_hydro_init(const HydroArgs &a, double e_origin, double dt0, hipStream_t stream);
-hipError_t launch_hydro_step(const HydroArgs &a, int hg_mode, bool eos_taf, hipStream_t stream);
+hipError_t launch_hydro_step(const HydroArgs &a, int hg_mode, int eos_mode, hipStream_t stream);
 
 }  // namespace hpac

@@ -74,8 +74,8 @@ class hpac_hydro_state(ctypes.Structure):
 
 class hpac_hydro_tech(ctypes.Structure):
     _fields_ = [("eos_history", ctypes.c_int32), ("eos_prediction", ctypes.c_int32),
-                ("eos_threshold", ctypes.c_float), ("hg_history", ctypes.c_int32),
-                ("hg_prediction", ctypes.c_int32), ("hg_threshold", ctypes.c_float),
+                ("eos_threshold", ctypes.c_float), ("eos_level", ctypes.c_int32), ("hg_history", ctypes.c_int32),
+                ("hg_prediction", ctypes.c_int32), ("hg_threshold", ctypes.c_float), ("hg_level", ctypes.c_int32),
                 ("perfo_kind", ctypes.c_int32), ("perfo_param", ctypes.c_int32),
                 ("perfo_items_per_lane", ctypes.c_int32)]
 
@@ -116,6 +116,8 @@ def lib():
     HP, HS, HT = (ctypes.POINTER(t) for t in (hpac_hydro_params, hpac_hydro_state, hpac_hydro_tech))
     L.hpac_hydro_waves.argtypes = [i32]
     L.hpac_hydro_waves.restype = i64
+    L.hpac_hydro_groups.argtypes = [i32, i32]
+    L.hpac_hydro_groups.restype = i64
     L.hpac_hydro_partials.argtypes = [i32]
     L.hpac_hydro_partials.restype = i64
     L.hpac_hydro_init.argtypes = [HP, ctypes.c_double, HS, vp]
@@ -355,6 +357,10 @@ def trace_fields(t):
 
 def hpac_hydro_waves(n):
     return lib().hpac_hydro_waves(n)
+
+
+def hpac_hydro_groups(n, level):
+    return lib().hpac_hydro_groups(n, _level(level))
 
 
 def hpac_hydro_partials(n):

@@ -25,16 +25,18 @@ def sedov_origin_energy(n, side=1.0, energy=1.0):
 
 class Tech:
     """Technique of the hydro regions: eos / hg = (history, prediction,
-    threshold) for TAF, perfo = (kind, param, items_per_lane) for the
-    hourglass region."""
+    threshold[, level]) for TAF, level "wave" (default) or "thread";
+    perfo = (kind, param, items_per_lane) for the hourglass region."""
 
     def __init__(self, eos=None, hg=None, perfo=None):
         self.eos, self.hg, self.perfo = eos, hg, perfo
-        t = hpac.hpac_hydro_tech()
+        t = hpac.hpac_hydro_tech(eos_level=hpac.LEVEL_WAVE, hg_level=hpac.LEVEL_WAVE)
         if eos:
             t.eos_history, t.eos_prediction, t.eos_threshold = int(eos[0]), int(eos[1]), float(eos[2])
+            t.eos_level = hpac._level(eos[3]) if len(eos) > 3 else hpac.LEVEL_WAVE
         if hg:
             t.hg_history, t.hg_prediction, t.hg_threshold = int(hg[0]), int(hg[1]), float(hg[2])
+            t.hg_level = hpac._level(hg[3]) if len(hg) > 3 else hpac.LEVEL_WAVE
         if perfo:
             kind = hpac.PERFO_KINDS[perfo[0]] if isinstance(perfo[0], str) else int(perfo[0])
             t.perfo_kind, t.perfo_param, t.perfo_items_per_lane = kind, int(perfo[1]), int(perfo[2])
@@ -60,19 +62,19 @@ class Hydro:
             setattr(self, f, torch.zeros(E, **f32))
         self.force = torch.zeros(24, E, **f32)
         t = self.tech
-        approx_hg = bool(t.hg) or bool(t.perfo and t.perfo[1])
-        self.fhg = torch.zeros(24, E, **f32) if approx_hg else None
+        self.fhg = torch.zeros(24, E, **f32) if t.hg else None
         i32 = dict(dtype=torch.int32, device=device)
+        # decision-group state: one entry per element covers both levels
         self.weos = torch.zeros(max(t.eos[0], 1) * 4, E, **f32) if t.eos else None
-        self.rho_eos = torch.zeros(self.W, **i32) if t.eos else None
-        self.z_eos = torch.zeros(self.W, **i32) if t.eos else None
+        self.rho_eos = torch.zeros(E, **i32) if t.eos else None
+        self.z_eos = torch.zeros(E, **i32) if t.eos else None
         self.whg = torch.zeros(max(t.hg[0], 1) * 24, E, **f32) if t.hg else None
-        self.rho_hg = torch.zeros(self.W, **i32) if t.hg else None
-        self.z_hg = torch.zeros(self.W, **i32) if t.hg else None
+        self.rho_hg = torch.zeros(E, **i32) if t.hg else None
+        self.z_hg = torch.zeros(E, **i32) if t.hg else None
         self.clock = torch.zeros(2, dtype=torch.float64, device=device)
         self.dt_partials = torch.zeros(hpac.hpac_hydro_partials(self.n), dtype=torch.float64, device=device)
-        self.dec_eos = torch.zeros(self.W, dtype=torch.int8, device=device)
-        self.dec_hg = torch.zeros(self.W, dtype=torch.int8, device=device)
+        self.dec_eos = torch.zeros(E, dtype=torch.int8, device=device)
+        self.dec_hg = torch.zeros(E, dtype=torch.int8, device=device)
         self.params = hpac.hpac_hydro_params(n=self.n, **self.par)
         self.steps = 0
         self._bind()

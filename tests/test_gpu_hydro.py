@@ -36,12 +36,17 @@ def _device():
     hpac.lib()
 
 
+def _group(t):
+    level = t[3] if len(t) > 3 else "wave"
+    return 1 if level in ("thread", hpac.LEVEL_THREAD) else 64
+
+
 def oracle_tech(tech):
     kw = {}
     if tech.eos:
-        kw["eos"] = tech.eos
+        kw["eos"] = tuple(tech.eos[:3]) + (_group(tech.eos),)
     if tech.hg:
-        kw["hg"] = tech.hg
+        kw["hg"] = tuple(tech.hg[:3]) + (_group(tech.hg),)
     if tech.perfo:
         kind = hpac.PERFO_KINDS[tech.perfo[0]] if isinstance(tech.perfo[0], str) else tech.perfo[0]
         kw["perfo"] = (kind, tech.perfo[1], tech.perfo[2])
@@ -87,8 +92,8 @@ def replay_step(h, band=1e-3):
     for region, on in (("eos", h.tech.eos), ("hg", h.tech.hg)):
         if not on:
             continue
-        gd = getattr(h, "dec_" + region).cpu().numpy()
         od = rec["dec_" + region]
+        gd = getattr(h, "dec_" + region).cpu().numpy()[:od.size]
         frag = rec["frag_" + region].astype(bool)
         dec[region] = (gd, od, frag)
     return errs, dec, s
@@ -155,6 +160,8 @@ TAF_CASES = [
     ("eos", Tech(eos=(4, 4, 0.01))),
     ("hourglass", Tech(hg=(4, 4, 0.05))),
     ("both", Tech(eos=(2, 8, 0.05), hg=(3, 2, 0.1))),
+    ("eos_thread", Tech(eos=(4, 4, 0.01, "thread"))),
+    ("both_thread", Tech(eos=(3, 2, 0.02, "thread"), hg=(2, 3, 0.05, "thread"))),
 ]
 
 
