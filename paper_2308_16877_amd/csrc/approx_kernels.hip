@@ -433,6 +433,7 @@ __global__ void __launch_bounds__(256) k_taf(KArgs a, int psize, float theta) {
     for (int o = 0; o < R::kOut; ++o) win[q][o] = 0.0f;
   int fill = 0;
   int rho = 0;  // remaining approximate steps (uniform per group)
+  bool prev_stable = false;
   WaveStats st;
   float xa[R::kIn], xb[R::kIn];
   load_first<R>(a, g, true, xa);
@@ -446,9 +447,14 @@ __global__ void __launch_bounds__(256) k_taf(KArgs a, int psize, float theta) {
     const bool lane_approx = active && stable;
     const bool computes = active && !stable;
     // Inputs of step k+1 are needed unless it is certainly approximate
-    // (this step is approximate with more to come).  After a passing vote the
-    // speculative load of step k+1 goes unused.
-    prefetch<R>(a, g, k + 1, !stable || rho == 1, xn);
+    // (this step is approximate with more to come).  At wave level, the
+    // first accurate step after an approximate run is the step whose vote
+    // most likely passes again: its prefetch waits for the vote, so that a
+    // passing vote loads nothing.  Elsewhere step k+1's loads are issued
+    // before step k computes, and a passing vote leaves them unused.
+    const bool late = LEVEL == kWaveLvl && !stable && prev_stable;
+    prev_stable = stable;
+    if (!late) prefetch<R>(a, g, k + 1, !stable || rho == 1, xn);
     bool crit = false, voted = false;
     if (lane_approx) store_outputs<R>(a, i, win[H - 1]);
     if (computes) {
@@ -485,6 +491,7 @@ __global__ void __launch_bounds__(256) k_taf(KArgs a, int psize, float theta) {
       pass = tally.decide(k, popc(vmask), popc(amask)) && !stable;
       wave_approx = stable && amask != 0;
     }
+    if (late) prefetch<R>(a, g, k + 1, !pass, xn);
     if (stable) rho -= 1;
     else if (pass) rho = psize;
     if (amask && (a.trace || a.counters)) {
