@@ -506,6 +506,87 @@ __global__ void __launch_bounds__(256) k_taf(KArgs a, int psize, float theta) {
   sink.end(st);
 }
 
+// Wave-level TAF as a loop over runs: one accurate step (region, window,
+// vote), then, if the wave votes to approximate, psize approximate steps
+// that only store the last output.  The inputs of the next accurate step are
+// loaded right after the vote: before the psize stores of a run, or, when
+// the vote fails, before the next step.  Only when the previous vote failed
+// is the next step's load issued speculatively before the region computes
+// (the vote is then likely to fail again); a pass wastes that load once.
+// Same decisions as k_taf at wave level.
+template <class R, int H>
+__global__ void __launch_bounds__(256) k_taf_wave(KArgs a, int psize, float theta) {
+  __shared__ unsigned long long sums[4];
+  const LaneGeom g;
+  const int lane = lane_id();
+  StatsSink sink{a.counters, sums};
+  sink.begin();
+  const double th = (double)theta;
+  const double th2 = th * th;
+  float win[H][R::kOut];  // win[H-1] is the newest accurate output
+#pragma unroll
+  for (int q = 0; q < H; ++q)
+#pragma unroll
+    for (int o = 0; o < R::kOut; ++o) win[q][o] = 0.0f;
+  int fill = 0;
+  bool prev_pass = false;
+  WaveStats st;
+  float x[R::kIn], xn[R::kIn];
+#pragma unroll
+  for (int j = 0; j < R::kIn; ++j) xn[j] = 0.0f;
+  load_first<R>(a, g, true, xn);
+  int k = 0;
+  while (k < a.ipt && g.wave_has(a, k)) {
+#pragma unroll
+    for (int j = 0; j < R::kIn; ++j) x[j] = xn[j];
+    const bool active = g.active(a, k);
+    const int64_t i = g.item(a, k);
+    if (!prev_pass && k + 1 < a.ipt && g.active(a, k + 1)) load_inputs<R>(a, g.item(a, k + 1), xn);
+    bool crit = false, voted = false;
+    if (active) {
+      float y[R::kOut];
+      R::eval(x, y);
+      store_outputs<R>(a, i, y);
+#pragma unroll
+      for (int q = 0; q + 1 < H; ++q)
+#pragma unroll
+        for (int o = 0; o < R::kOut; ++o) win[q][o] = win[q + 1][o];
+#pragma unroll
+      for (int o = 0; o < R::kOut; ++o) win[H - 1][o] = y[o];
+      fill = fill < H ? fill + 1 : H;
+      if (fill == H) {
+        voted = true;
+        crit = rsd_below<H, R::kOut>(win, th2, th > 0.0);
+      }
+    }
+    const uint64_t amask = ballot(active);
+    const uint64_t vmask = ballot(crit);
+    const bool any_vote = ballot(voted) != 0;
+    const bool pass = any_vote && majority(popc(vmask), popc(amask));
+    const int next = pass ? k + psize + 1 : k + 1;
+    if ((prev_pass || pass) && next < a.ipt && g.active(a, next)) load_inputs<R>(a, g.item(a, next), xn);
+    if (a.trace || a.counters) {
+      st.add(popc(amask), 0, false);
+      if (a.trace && lane == 0)
+        a.trace[g.trace_index(a, k)] = trace_word(any_vote ? popc(vmask) : 0, 0, -1, false, any_vote);
+    }
+    if (pass) {
+      for (int kk = k + 1; kk < next && kk < a.ipt && g.wave_has(a, kk); ++kk) {
+        const bool act = g.active(a, kk);
+        if (act) store_outputs<R>(a, g.item(a, kk), win[H - 1]);
+        if (a.trace || a.counters) {
+          const int nact = popc(ballot(act));
+          st.add(nact, nact, true);
+          if (a.trace && lane == 0) a.trace[g.trace_index(a, kk)] = trace_word(0, nact, -1, true, false);
+        }
+      }
+    }
+    prev_pass = pass;
+    k = next;
+  }
+  sink.end(st);
+}
+
 // ------------------------------------------------------------------ probe
 
 __global__ void __launch_bounds__(256) k_copy(const float4 *__restrict__ src, float4 *__restrict__ dst, int64_t n4) {
@@ -643,7 +724,10 @@ hipError_t launch_iact(const LaunchCfg &c, const KArgs &a, int level, int table_
 
 template <class R, int LEVEL, int H>
 static void taf_go(const LaunchCfg &c, const KArgs &a, int p, float thr) {
-  hipLaunchKernelGGL((k_taf<R, LEVEL, H>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a, p, thr);
+  if (LEVEL == kWaveLvl)
+    hipLaunchKernelGGL((k_taf_wave<R, H>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a, p, thr);
+  else
+    hipLaunchKernelGGL((k_taf<R, LEVEL, H>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a, p, thr);
 }
 
 template <class R, int LEVEL>
