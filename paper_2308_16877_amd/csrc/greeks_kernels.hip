@@ -8,7 +8,7 @@
 // which moves 48 instead of 68 bytes per item.  Both contract with the same
 // separately rounded products and sum, so on the same derivatives they agree
 // bit for bit.
-#include "launch.hpp"
+#include "launch_greeks.hpp"
 #include "region_bs.hpp"
 
 namespace hpac {

@@ -3,6 +3,9 @@
 // the thread-local error message.  Declarations and semantics: hpac.h.
 #include "../../include/hpac.h"
 #include "launch.hpp"
+#include "launch_greeks.hpp"
+#include "launch_hydro.hpp"
+#include "launch_mlp.hpp"
 
 #include <math.h>
 #include <stdarg.h>

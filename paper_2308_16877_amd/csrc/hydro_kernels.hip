@@ -29,7 +29,7 @@
 // An approximate EOS step reads only the countdown; an approximate
 // hourglass step adds the last accurate hourglass forces instead of
 // computing them.  A perforated hourglass iteration adds nothing.
-#include "launch.hpp"
+#include "launch_hydro.hpp"
 #include "wave.hpp"
 
 namespace hpac {

@@ -1,0 +1,41 @@
+// Launchers of the Lagrangian hydro kernels (hydro_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hpac {
+
+// Lagrangian hydro (hydro_kernels.hip).  Region modes:
+constexpr int kHgExact = 0, kHgTafWave = 1, kHgTafThread = 2, kHgPerfo = 3;
+constexpr int kEosExact = 0, kEosTafWave = 1, kEosTafThread = 2;
+
+struct HydroArgs {
+  int n;                  // elements per side
+  int64_t E, Nn, W;       // elements, nodes, waves of the element loop (one element per lane)
+  float h;                // initial edge of an element
+  float gamma, cq, cl, khg;
+  double gamma_d, cfl, growth, dvmax;
+  float *x[3], *u[3], *un[3];
+  float *mnode, *e, *p, *q, *c, *vol, *mass, *force, *fhg;
+  float *weos;
+  int32_t *rho_eos, *z_eos;
+  float *whg;
+  int32_t *rho_hg, *z_hg;
+  double *clock, *dt_partials;
+  int8_t *dec_eos, *dec_hg;
+  // technique of this step
+  int eos_h, eos_p;
+  float eos_theta;
+  int hg_h, hg_p;
+  float hg_theta;
+  int perfo_kind, perfo_param;
+  int hg_ipt;      // items per lane of the force kernel's element loop
+  int64_t hg_L;    // its logical lanes
+  int32_t step;    // timestep index (perforation offset)
+};
+int64_t hydro_lanes(int64_t E, int ipt);
+int64_t hydro_partials(int64_t E);
+hipError_t launch_hydro_init(const HydroArgs &a, double e_origin, double dt0, hipStream_t stream);
+hipError_t launch_hydro_step(const HydroArgs &a, int hg_mode, int eos_mode, hipStream_t stream);
+
+}  // namespace hpac

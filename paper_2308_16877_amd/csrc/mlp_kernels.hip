@@ -15,7 +15,7 @@
 //                partial sums per workgroup (deterministic, no atomics).
 //  k_mlp_adam    sums the partials and applies one Adam step to the FP32
 //                master weights.
-#include "launch.hpp"
+#include "launch_mlp.hpp"
 #include "region_bs.hpp"
 #include "wave.hpp"
 

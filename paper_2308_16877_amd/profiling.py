@@ -4,12 +4,15 @@ profiles/.
   python -m paper_2308_16877_amd.profiling trace <kernel_stats.csv> <kernel_trace.csv> <bench.json> <out.txt> "<command>"
   python -m paper_2308_16877_amd.profiling traffic <fetch counter_collection.csv> <write counter_collection.csv> \
         <kernel-name-substring> <workload> <out.json> "<fetch command>" "<write command>"
+  python -m paper_2308_16877_amd.profiling valu <sq counter_collection.csv> <kernel-name-substring> <workload> \
+        <items per dispatch> <out.json> "<command>"
+  python -m paper_2308_16877_amd.profiling kernels <kernel_stats.csv> <name-substring> <out.txt> "<title>" "<command>"
 
 The traffic summary scales each kernel's FETCH_SIZE and WRITE_SIZE (KiB per
 dispatch) by what the same counter reports for the plain copy probe of a
-known size (bench.py --pmc-probe), and records the hash of the kernel sources
-it was measured on, so that the benchmark reports it only while the kernels
-are unchanged.
+known size (bench.py --pmc-probe), and records the hash of the kernel's sources
+(its translation unit and the headers it includes) it was measured on, so
+that the benchmark reports it only while that code is unchanged.
 """
 import csv
 import hashlib
@@ -18,15 +21,38 @@ import os
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SOURCES = ("approx_kernels.hip", "region_bs.hpp", "wave.hpp", "launch.hpp")
+CSRC = os.path.join(ROOT, "paper_2308_16877_amd", "csrc")
 COPY_KERNEL = "k_copy"
 COPY_BYTES = 256 << 20
+# translation unit of each kernel family (by kernel-name prefix)
+KERNEL_UNITS = (("k_hydro", "hydro_kernels.hip"), ("k_mlp", "mlp_kernels.hip"), ("k_bs_", "greeks_kernels.hip"),
+                ("k_", "approx_kernels.hip"))
 
 
-def kernel_source_sha():
+def _unit_files(unit):
+    """The translation unit and every csrc header it includes, transitively."""
+    seen, todo = [], [unit]
+    while todo:
+        f = todo.pop()
+        if f in seen:
+            continue
+        seen.append(f)
+        for line in open(os.path.join(CSRC, f)):
+            line = line.strip()
+            if line.startswith('#include "'):
+                inc = line.split('"')[1]
+                if os.path.exists(os.path.join(CSRC, inc)):
+                    todo.append(inc)
+    return sorted(seen)
+
+
+def kernel_source_sha(kernel="k_exact"):
+    """Hash of the sources a kernel is compiled from; a counter summary is
+    only used while it matches."""
+    unit = next(u for prefix, u in KERNEL_UNITS if kernel.startswith(prefix))
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_2308_16877_amd", "csrc", f), "rb").read())
+    for f in _unit_files(unit):
+        h.update(open(os.path.join(CSRC, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -35,9 +61,19 @@ def short_name(name):
     return base
 
 
+BS_KERNELS = ("k_exact", "k_iact", "k_taf", "k_taf_wave", "k_perfo", "k_perfo_dense")
+
+
+def _is_bs(name):
+    return any(_kernel_match(name, k) for k in BS_KERNELS)
+
+
 def trace_summary(stats_csv, trace_csv, bench_json, out_txt, command):
-    stats = list(csv.DictReader(open(stats_csv)))
-    trace = list(csv.DictReader(open(trace_csv)))
+    """Kernel statistics and per-dispatch durations of the Black-Scholes
+    technique kernels in a benchmark run, beside the HIP-event averages that
+    run printed."""
+    stats = [r for r in csv.DictReader(open(stats_csv)) if _is_bs(r["Name"])]
+    trace = [r for r in csv.DictReader(open(trace_csv)) if _is_bs(r.get("Kernel_Name", ""))]
     bench = json.loads([l for l in open(bench_json) if l.startswith("{")][-1])
     lines = ["# rocprofv3 kernel-trace summary", "", "command (run from the repository root on one MI355X):", "",
              "    " + command, "", "kernel | calls | avg us | min us | max us | share %", "--- | --- | --- | --- | --- | ---"]
@@ -73,8 +109,8 @@ def traffic_summary(fetch_csv, write_csv, kernel_sub, workload, out_json, fetch_
     res = {}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rows = _pmc(path, counter)
-        copy = [float(r["Counter_Value"]) for r in rows if COPY_KERNEL in r["Kernel_Name"]]
-        kern = [float(r["Counter_Value"]) for r in rows if kernel_sub in r["Kernel_Name"] and COPY_KERNEL not in r["Kernel_Name"]]
+        copy = [float(r["Counter_Value"]) for r in rows if _kernel_match(r["Kernel_Name"], COPY_KERNEL)]
+        kern = [float(r["Counter_Value"]) for r in rows if _kernel_match(r["Kernel_Name"], kernel_sub)]
         if not copy or not kern:
             raise SystemExit("no %s rows for %s or the copy probe in %s" % (counter, kernel_sub, path))
         copy_kib = sum(copy) / len(copy)
@@ -83,7 +119,7 @@ def traffic_summary(fetch_csv, write_csv, kernel_sub, workload, out_json, fetch_
         scale = (COPY_BYTES / 1024.0) / copy_kib
         res[counter] = {"kib_per_dispatch": kib, "copy_probe_kib_per_dispatch": copy_kib, "scale": scale,
                         "bytes_per_dispatch": kib * 1024.0 * scale, "dispatches": len(kern)}
-    out = {"kernel": kernel_sub, "workload": workload, "kernel_source_sha": kernel_source_sha(),
+    out = {"kernel": kernel_sub, "workload": workload, "kernel_source_sha": kernel_source_sha(kernel_sub),
            "hbm_bytes_per_launch": res["FETCH_SIZE"]["bytes_per_dispatch"] + res["WRITE_SIZE"]["bytes_per_dispatch"],
            "fetch": res["FETCH_SIZE"], "write": res["WRITE_SIZE"],
            "commands": [fetch_cmd, write_cmd],
@@ -92,10 +128,54 @@ def traffic_summary(fetch_csv, write_csv, kernel_sub, workload, out_json, fetch_
     return out
 
 
+def _kernel_match(name, sub):
+    base = short_name(name)
+    return base.startswith("hpac::" + sub + "<") or base == "hpac::" + sub
+
+
+def valu_summary(sq_csv, kernel_sub, workload, items, out_json, command):
+    """Vector instructions issued per dispatch (SQ_INSTS_VALU, wave
+    instructions, summed over the chip) and the other SQ counters of the same
+    run, for the kernel whose name is hpac::<kernel_sub><...>."""
+    rows = [r for r in csv.DictReader(open(sq_csv)) if _kernel_match(r["Kernel_Name"], kernel_sub)]
+    if not rows:
+        raise SystemExit("no rows for %s in %s" % (kernel_sub, sq_csv))
+    per = {}
+    for r in rows:
+        per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    avg = {c: sum(v) / len(v) for c, v in per.items()}
+    items = int(items)
+    out = {"kernel": kernel_sub, "workload": workload, "kernel_source_sha": kernel_source_sha(kernel_sub),
+           "dispatches": len(per.get("SQ_INSTS_VALU", [])), "counters_per_dispatch": avg,
+           "lane_instructions_per_dispatch": avg["SQ_INSTS_VALU"] * 64.0,
+           "items_per_dispatch": items, "valu_instructions_per_item": avg["SQ_INSTS_VALU"] * 64.0 / items,
+           "command": command}
+    json.dump(out, open(out_json, "w"), indent=1)
+    return out
+
+
+def kernels_summary(stats_csv, sub, out_txt, title, command):
+    """Per-kernel rocprofv3 statistics of the hpac kernels whose name contains sub."""
+    stats = list(csv.DictReader(open(stats_csv)))
+    lines = ["# " + title, "", "command (run from the repository root on one MI355X):", "", "    " + command, "",
+             "kernel | calls | avg us | min us | max us | total us", "--- | --- | --- | --- | --- | ---"]
+    for r in stats:
+        if "hpac" not in r["Name"] or sub not in r["Name"]:
+            continue
+        lines.append("%s | %s | %.2f | %.2f | %.2f | %.1f" % (
+            short_name(r["Name"]), r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+            float(r["MaxNs"]) / 1e3, float(r["TotalDurationNs"]) / 1e3))
+    open(out_txt, "w").write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace_summary(*sys.argv[2:7])
     elif sys.argv[1] == "traffic":
         print(json.dumps(traffic_summary(*sys.argv[2:9]), indent=1))
+    elif sys.argv[1] == "valu":
+        print(json.dumps(valu_summary(*sys.argv[2:8]), indent=1))
+    elif sys.argv[1] == "kernels":
+        kernels_summary(*sys.argv[2:7])
     else:
         raise SystemExit(__doc__)
