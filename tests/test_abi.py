@@ -118,3 +118,75 @@ def test_zero_items_is_a_no_op():
     hpac.hpac_taf([FAKE] * 5, [FAKE] * 2, 4, 4, 0.01, n=0)
     hpac.hpac_iact([FAKE] * 5, [FAKE] * 2, 8, 0.05, n=0)
     hpac.hpac_perfo([FAKE] * 5, [FAKE] * 2, "small", 10, n=0)
+
+
+def hydro_state(**over):
+    s = hpac.hpac_hydro_state()
+    for d in range(3):
+        s.x[d] = FAKE
+        s.u[d] = FAKE
+        s.unew[d] = FAKE
+    for f in ("mnode", "e", "p", "q", "c", "vol", "mass", "force", "fhg", "weos", "rho_eos", "z_eos", "whg",
+              "rho_hg", "z_hg"):
+        setattr(s, f, FAKE)
+    s.clock = FAKE
+    s.dt_partials = FAKE
+    for k, v in over.items():
+        setattr(s, k, v)
+    return s
+
+
+def hydro_params(**over):
+    p = dict(n=10, side=1.0, gamma=1.4, cq=1.5, cl=0.25, khg=0.1, cfl=0.3, growth=1.1, dvmax=0.1, dt0=1e-7)
+    p.update(over)
+    return hpac.hpac_hydro_params(**p)
+
+
+def hydro_tech(**over):
+    t = hpac.hpac_hydro_tech(eos_level=hpac.LEVEL_WAVE, hg_level=hpac.LEVEL_WAVE)
+    for k, v in over.items():
+        setattr(t, k, v)
+    return t
+
+
+def test_hydro_sizes():
+    assert hpac.hpac_hydro_waves(90) == (90 ** 3 + 63) // 64
+    assert hpac.hpac_hydro_groups(90, hpac.LEVEL_THREAD) == 90 ** 3
+    assert hpac.hpac_hydro_groups(90, hpac.LEVEL_WAVE) == (90 ** 3 + 63) // 64
+    assert hpac.hpac_hydro_groups(90, hpac.LEVEL_BLOCK) == -1
+    assert hpac.hpac_hydro_partials(90) == ((90 ** 3 + 63) // 64 * 64 + 255) // 256
+    assert hpac.hpac_hydro_waves(0) == -1 and hpac.hpac_hydro_waves(1001) == -1
+
+
+def hstep(*a):
+    return hpac.hpac_hydro_step(*a, stream=0)  # a stream handle that is never used: validation fails first
+
+
+def hinit(*a):
+    return hpac.hpac_hydro_init(*a, stream=0)
+
+
+def test_invalid_hydro_arguments_are_rejected():
+    E = hpac.HPAC_EINVAL
+    S, P, T = hydro_state(), hydro_params(), hydro_tech()
+    for bad in (dict(n=0), dict(n=1001), dict(gamma=1.0), dict(cfl=0.0), dict(growth=0.5), dict(dt0=0.0),
+                dict(side=float("nan")), dict(khg=-1.0)):
+        expect(E, hstep, hydro_params(**bad), T, 0, S)
+        expect(E, hinit, hydro_params(**bad), 1.0, S)
+    expect(E, hinit, P, -1.0, S)
+    expect(E, hinit, P, float("inf"), S)
+    expect(E, hstep, P, T, -1, S)
+    expect(E, hstep, P, T, 0, hydro_state(e=0))
+    expect(E, hstep, P, T, 0, hydro_state(force=FAKE + 2))
+    expect(E, hstep, P, T, 0, hydro_state(clock=FAKE + 4))
+    for bad in (dict(eos_history=9, eos_prediction=1), dict(eos_history=2, eos_prediction=0),
+                dict(hg_history=-1), dict(eos_history=2, eos_prediction=2, eos_threshold=-0.1),
+                dict(eos_history=2, eos_prediction=2, eos_level=hpac.LEVEL_BLOCK),
+                dict(hg_history=2, hg_prediction=2, perfo_param=2, perfo_items_per_lane=2),
+                dict(perfo_kind=4, perfo_param=2, perfo_items_per_lane=2),
+                dict(perfo_kind=hpac.PERFO_INI, perfo_param=101, perfo_items_per_lane=1),
+                dict(perfo_param=2, perfo_items_per_lane=0), dict(perfo_param=2, perfo_items_per_lane=65)):
+        expect(E, hstep, P, hydro_tech(**bad), 0, S)
+    expect(E, hstep, P, hydro_tech(eos_history=2, eos_prediction=2), 0, hydro_state(weos=0))
+    expect(E, hstep, P, hydro_tech(hg_history=2, hg_prediction=2), 0, hydro_state(fhg=0))
+    expect(E, hstep, P, hydro_tech(hg_history=2, hg_prediction=2), 0, hydro_state(z_hg=0))

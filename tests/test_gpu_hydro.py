@@ -220,3 +220,19 @@ def test_full_mesh_steps():
         approx.append((gd == 1).mean())
     say("90^3 approximate wave fraction at steps 8..10: %s" % approx)
     assert approx[0] == 0 and approx[1] > 0.9  # the quiet mesh is approximated
+
+
+@pytest.mark.parametrize("n,tech", [
+    (1, Tech()), (2, Tech(eos=(2, 2, 0.05))), (5, Tech(eos=(2, 3, 0.05), hg=(2, 2, 0.1))),
+    (5, Tech(eos=(2, 3, 0.05, "thread"), hg=(3, 1, 0.1, "thread"))), (7, Tech(perfo=("small", 3, 4))),
+    (9, Tech(perfo=("large", 2, 64))),
+], ids=["n1", "n2_eos", "n5_both_wave", "n5_both_thread", "n7_small", "n9_large_ipt64"])
+def test_small_and_ragged_meshes(n, tech):
+    """Meshes of one element, of fewer elements than a wave, and with a
+    ragged last wave (125 = 64 + 61 elements), stepped and replayed."""
+    h = Hydro(n, tech=tech)
+    for k in range(30):
+        errs, dec, _ = replay_step(h)
+        check_errs(errs, "n=%d step %d" % (n, k))
+        for region, (gd, od, frag) in dec.items():
+            assert np.all((gd == od) | frag), (region, k)
