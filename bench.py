@@ -14,7 +14,8 @@ speedup over the exact kernel and MAPE against the exact kernel's outputs,
 the roofline of the dominant kernel (HIP-event durations on the launch
 stream), and the CPU oracle timed on a bounded sample.  Further legs, each
 at its own accuracy: the Greeks adjoint, the reduced-precision variants,
-the MLP surrogate and the Sedov hydro under TAF and perforation.
+the decision hierarchy and items-per-lane study, the MLP surrogate and the
+Sedov hydro under TAF and perforation.
 """
 import argparse
 import json
@@ -312,6 +313,57 @@ def surrogate_leg(torch, hpac, n):
             "fallback_count": int(s.count.item())}
 
 
+def technique_point(torch, hpac, x_copies, n, fn, ipt, params, exact_out, steps=6):
+    """Time one technique configuration (HIP events, rotating input copies)
+    and measure its approximated fraction and MAPE against exact_out."""
+    dev = x_copies[0][0].device
+    out = [torch.zeros(n, dtype=torch.float32, device=dev) for _ in range(2)]
+    stream = torch.cuda.current_stream()
+    preps = [hpac.prepare(fn, xs, out, items_per_lane=ipt, block_size=256, stream=stream, **params)
+             for xs in x_copies]
+    t = time_pairs(torch, {"p": preps}, steps, 1)["p"] / len(preps)
+    cnt = torch.zeros(hpac.NUM_COUNTERS, dtype=torch.int64, device=dev)
+    {"exact": hpac.hpac_exact, "iact": hpac.hpac_iact, "taf": hpac.hpac_taf, "perfo": hpac.hpac_perfo}[fn](
+        x_copies[0], out, items_per_lane=ipt, block_size=256, counters=cnt, **params)
+    torch.cuda.synchronize()
+    c = cnt.cpu().tolist()
+    return {"ms": t, "approx_frac": c[1] / max(c[0], 1), "mape": mape_torch(torch, exact_out, out)}
+
+
+def hierarchy_and_ipt_leg(torch, hpac, n):
+    """The decision hierarchy (thread, wave, block) and the items-per-lane
+    trade-off of the paper's insights, on the structured variants where the
+    techniques find reuse: TAF on the lane-periodic inputs, iACT on the
+    wave-periodic ones.  Times are per launch over 2^24 items; speedups are
+    against the exact kernel on the same inputs."""
+    import numpy as np  # noqa: F401
+    from paper_2308_16877_amd import inputs
+    dev = "cuda:0"
+    res = {}
+    for vname, period, tech, params in (
+            ("lane_periodic_1024", 1024, "taf", dict(history_size=4, prediction_size=4, rsd_threshold=0.01)),
+            ("wave_periodic_2", 2, "iact", dict(table_size=8, threshold=0.05, tables_per_wave=1))):
+        xs = inputs.periodic(n, period, jitter=1e-3)
+        copies = [[torch.from_numpy(c).to(dev) for c in xs] for _ in range(3)]
+        ex = [torch.zeros(n, dtype=torch.float32, device=dev) for _ in range(2)]
+        hpac.hpac_exact(copies[0], ex, items_per_lane=1)
+        exact_ms = technique_point(torch, hpac, copies, n, "exact", 1, {}, ex)["ms"]
+        levels = {}
+        for level in ("thread", "wave", "block"):
+            r = technique_point(torch, hpac, copies, n, tech, 16, dict(params, level=level), ex)
+            r["speedup_vs_exact"] = exact_ms / r["ms"]
+            levels[level] = r
+        ipts = {}
+        for ipt in (1, 2, 4, 8, 16, 32, 64):
+            r = technique_point(torch, hpac, copies, n, tech, ipt, dict(params, level="wave"), ex)
+            r["speedup_vs_exact"] = exact_ms / r["ms"]
+            ipts[str(ipt)] = r
+        res[tech] = {"variant": vname, "params": params, "exact_ms": exact_ms, "levels_at_ipt16": levels,
+                     "items_per_lane_at_wave_level": ipts}
+        del copies
+    return res
+
+
 HYDRO_TECHS = {
     # name: hydro technique arguments
     "exact": {},
@@ -500,8 +552,10 @@ def main():
         print("[bench] precision variants", file=sys.stderr, flush=True)
         precision = precision_leg(torch, hpac, x_copies[0], n, max(args.steps // 2, 3))
 
-    sur = hydro = None
+    sur = hydro = hier = None
     if not args.no_structured:
+        print("[bench] hierarchy and items-per-lane study", file=sys.stderr, flush=True)
+        hier = hierarchy_and_ipt_leg(torch, hpac, n)
         print("[bench] surrogate", file=sys.stderr, flush=True)
         sur = surrogate_leg(torch, hpac, n)
         print("[bench] hydro", file=sys.stderr, flush=True)
@@ -538,6 +592,7 @@ def main():
         "structured_locality": structured,
         "greeks": greeks,
         "precision": precision,
+        "hierarchy_and_items_per_lane": hier,
         "surrogate": sur,
         "hydro": hydro,
     }
