@@ -3,8 +3,8 @@
 
 Only the test suite, the smoke check and the benchmark's CPU-baseline leg
 may import this package.  The GPU library never calls it and shares no code
-with it.  The arithmetic lives in ``oracle.c`` and ``hydro.c`` (plain C, FP64, built
-with gcc); this module only marshals numpy arrays into them.
+with it.  The arithmetic lives in ``oracle.c``, ``hydro.c`` and ``binomial.c`` (plain
+C, FP64, built with gcc); this module only marshals numpy arrays into them.
 
 Conventions: inputs are float32 columns (the region's declared input type),
 region values are float64.  ``region_values_f32out`` rounds the exact FP64
@@ -18,7 +18,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRCS = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "hydro.c")]
+_SRCS = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "hydro.c"), os.path.join(_HERE, "binomial.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -77,6 +77,8 @@ def _load():
     lib.or_mlp_forward.argtypes = [i64, P, P, P, P, P, P, i32, i32, P]
     lib.or_mlp_loss_grad.restype = f64
     lib.or_mlp_loss_grad.argtypes = [i64, P, P, P, P, P, P, P, i32, P]
+    lib.or_binomial.restype = None
+    lib.or_binomial.argtypes = [i64, P, P, P, P, P, i32, i32, P, P, P]
     lib.hy_init.restype = ctypes.c_int
     lib.hy_init.argtypes = [P, f64, P]
     lib.hy_step.restype = ctypes.c_int
@@ -429,3 +431,15 @@ def hex_hourglass(xc, uc, rho, c, khg):
     f = np.zeros((8, 3))
     _load().hy_hex_hourglass(_ptr(xc), _ptr(uc), float(rho), float(c), float(khg), _ptr(f))
     return f
+
+
+# ------------------------------------------------------------ binomial
+
+def binomial(S, K, T, r, v, steps, american=True):
+    """(call, put, scale) of the Cox-Ross-Rubinstein tree with `steps` time
+    steps, American or European exercise; scale = S + K e^{-rT}."""
+    cols = _as_f64_cols([S, K, T, r, v])
+    n = cols[0].size
+    C, P, sc = np.zeros(n), np.zeros(n), np.zeros(n)
+    _load().or_binomial(n, *[_ptr(c) for c in cols], int(steps), int(bool(american)), _ptr(C), _ptr(P), _ptr(sc))
+    return C, P, sc
