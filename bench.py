@@ -14,8 +14,8 @@ speedup over the exact kernel and MAPE against the exact kernel's outputs,
 the roofline of the dominant kernel (HIP-event durations on the launch
 stream), and the CPU oracle timed on a bounded sample.  Further legs, each
 at its own accuracy: the Greeks adjoint, the reduced-precision variants,
-the decision hierarchy and items-per-lane study, the MLP surrogate and the
-Sedov hydro under TAF and perforation.
+the decision hierarchy and items-per-lane study, the Binomial Options
+workload, the MLP surrogate and the Sedov hydro under TAF and perforation.
 """
 import argparse
 import json
@@ -364,6 +364,50 @@ def hierarchy_and_ipt_leg(torch, hpac, n):
     return res
 
 
+BO_TECHS = {
+    # name: (entry point, options per unit, parameters)
+    "exact": ("exact", 1, {}),
+    "iact": ("iact", 16, dict(table_size=8, threshold=0.05)),
+    "taf": ("taf", 16, dict(history_size=4, prediction_size=4, rsd_threshold=0.01)),
+    "perfo": ("perfo", 10, dict(kind="small", param=10)),
+}
+
+
+def binomial_leg(torch, hpac, n=65536, steps=512):
+    """American call and put on a 512-step tree for 65,536 options, one
+    wavefront per option: the portfolio workload (pool of 1,024 tuples, 1e-3
+    jitter) and a structured variant in which every unit (wavefront) of the
+    16-options-per-unit techniques sees one tuple at every option.  Per technique: ms, options/s, speedup over the
+    exact tree, approximated fraction and MAPE against the exact tree."""
+    from paper_2308_16877_amd import inputs
+    dev = "cuda:0"
+    res = {}
+    units = hpac.hpac_bo_units(n, 16)
+    for vname, x in (("portfolio_pool1024", inputs.portfolio(n, 1024)),
+                     ("unit_periodic", inputs.periodic(n, units, jitter=1e-3))):
+        xd = [torch.from_numpy(c).to(dev) for c in x]
+        ex = [torch.zeros(n, dtype=torch.float32, device=dev) for _ in range(2)]
+        hpac.hpac_bo_exact(xd, ex, steps, items_per_lane=1)
+        out = {}
+        for name, (fn, ipt, params) in BO_TECHS.items():
+            f = {"exact": hpac.hpac_bo_exact, "iact": hpac.hpac_bo_iact, "taf": hpac.hpac_bo_taf,
+                 "perfo": hpac.hpac_bo_perfo}[fn]
+            o = [torch.zeros(n, dtype=torch.float32, device=dev) for _ in range(2)]
+            call = (lambda f=f, o=o, ipt=ipt, params=params: f(xd, o, steps, items_per_lane=ipt, **params))
+            ms = time_pairs(torch, {"t": [call]}, 3, 1)["t"]
+            cnt = torch.zeros(hpac.NUM_COUNTERS, dtype=torch.int64, device=dev)
+            f(xd, o, steps, items_per_lane=ipt, counters=cnt, **params)
+            torch.cuda.synchronize()
+            c = cnt.cpu().tolist()
+            out[name] = {"ms": ms, "options_per_s": n / (ms * 1e-3), "approx_frac": c[1] / max(c[0], 1),
+                         "mape_vs_exact": mape_torch(torch, ex, o), "items_per_lane": ipt, "params": params}
+        for name in out:
+            out[name]["speedup_vs_exact"] = out["exact"]["ms"] / out[name]["ms"]
+        res[vname] = out
+    return {"workload": "American call+put, %d-step CRR tree, %d options, one wavefront per option" % (steps, n),
+            "variants": res}
+
+
 HYDRO_TECHS = {
     # name: hydro technique arguments
     "exact": {},
@@ -552,10 +596,12 @@ def main():
         print("[bench] precision variants", file=sys.stderr, flush=True)
         precision = precision_leg(torch, hpac, x_copies[0], n, max(args.steps // 2, 3))
 
-    sur = hydro = hier = None
+    sur = hydro = hier = bo = None
     if not args.no_structured:
         print("[bench] hierarchy and items-per-lane study", file=sys.stderr, flush=True)
         hier = hierarchy_and_ipt_leg(torch, hpac, n)
+        print("[bench] binomial options", file=sys.stderr, flush=True)
+        bo = binomial_leg(torch, hpac)
         print("[bench] surrogate", file=sys.stderr, flush=True)
         sur = surrogate_leg(torch, hpac, n)
         print("[bench] hydro", file=sys.stderr, flush=True)
@@ -593,6 +639,7 @@ def main():
         "greeks": greeks,
         "precision": precision,
         "hierarchy_and_items_per_lane": hier,
+        "binomial_options": bo,
         "surrogate": sur,
         "hydro": hydro,
     }

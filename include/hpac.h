@@ -66,6 +66,10 @@ typedef int32_t hpac_status;
  *         to the nearest BF16). */
 #define HPAC_REGION_BS_PRICE_F16 2
 #define HPAC_REGION_BS_PRICE_BF16 3
+/* HPAC_REGION_BINOMIAL: the paper's Binomial Options region (section 4,
+ * Table 1): call and put on a Cox-Ross-Rubinstein tree (see hpac_bo_*,
+ * which alone take it).  in (5) and out (2) as HPAC_REGION_BS_PRICE, FP32. */
+#define HPAC_REGION_BINOMIAL 4
 
 /* Element type of every column of a call (both inputs and outputs).
  * HPAC_REGION_BS_PRICE takes any of the three; _F16 takes F32 or F16; _BF16
@@ -331,6 +335,40 @@ hpac_status hpac_hydro_init(const hpac_hydro_params *params, double e_origin, co
  * Fields a technique needs must be non-NULL (HPAC_EINVAL otherwise). */
 hpac_status hpac_hydro_step(const hpac_hydro_params *params, const hpac_hydro_tech *tech, int32_t step,
                             const hpac_hydro_state *state, int8_t *dec_eos, int8_t *dec_hg, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Binomial Options.  One wavefront prices one option on an N-step
+ * Cox-Ross-Rubinstein tree (dt = T/N, u = exp(v sqrt(dt)), d = 1/u,
+ * p = (exp(r dt) - d) / (u - d); American: each node takes the larger of
+ * its continuation and exercise values), 1 <= N <= 1023.  The paper's
+ * benchmark has one group of threads per option and decides per option
+ * (section 4.1); here the wavefront is that group and the decision unit:
+ * unit u of hpac_bo_units(n, io->items_per_lane) units processes options
+ * u + k * units, k < items_per_lane, and decides alone for each (the thread
+ * level of section 3.1.2 with the wavefront as the thread).  io->region must
+ * be HPAC_REGION_BINOMIAL and io->dtype HPAC_F32; io->block_size (64..256)
+ * sets the units per workgroup.  io->trace, if given, receives one word per
+ * (unit, k) at trace[unit * items_per_lane + k] (bit 31 visited, bit 24
+ * approximated or skipped, bit 25 voted or inserted, bit 0 criterion held);
+ * io->counters as for the other techniques, per option.
+ *   iACT: a table of table_size (1..32) entries per unit, in FP32 with the
+ *     squared-distance rounding of hpac_iact; the nearest entry (lowest slot
+ *     on ties) is reused when its distance is below the threshold; a unit
+ *     that computed inserts its option round-robin.
+ *   TAF: per unit, a window of its last history_size (1..8) accurate
+ *     outputs, FP64 RSD test, prediction_size approximate options after a
+ *     passing test.
+ *   Perforation: herded over the unit's option loop as in hpac_perfo; a
+ *     skipped option is neither read nor written.
+ * ------------------------------------------------------------------------ */
+int64_t hpac_bo_units(int64_t n, int32_t items_per_lane);
+hpac_status hpac_bo_exact(const hpac_region_io *io, int32_t steps, int32_t american);
+hpac_status hpac_bo_iact(const hpac_region_io *io, int32_t steps, int32_t american, int32_t table_size,
+                         float threshold);
+hpac_status hpac_bo_taf(const hpac_region_io *io, int32_t steps, int32_t american, int32_t history_size,
+                        int32_t prediction_size, float rsd_threshold);
+hpac_status hpac_bo_perfo(const hpac_region_io *io, int32_t steps, int32_t american, int32_t kind, int32_t param,
+                          int32_t offset);
 
 /* Number of logical lanes L for n items at items_per_lane (see above);
  * -1 on invalid arguments. */

@@ -14,7 +14,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhpac.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["hpac_abi.hip", "approx_kernels.hip", "greeks_kernels.hip", "mlp_kernels.hip", "hydro_kernels.hip"]
+SOURCES = ["hpac_abi.hip", "approx_kernels.hip", "greeks_kernels.hip", "mlp_kernels.hip", "hydro_kernels.hip",
+           "binomial_kernels.hip"]
 
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 instructions.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -3,6 +3,7 @@
 // the thread-local error message.  Declarations and semantics: hpac.h.
 #include "../../include/hpac.h"
 #include "launch.hpp"
+#include "launch_binomial.hpp"
 #include "launch_greeks.hpp"
 #include "launch_hydro.hpp"
 #include "launch_mlp.hpp"
@@ -91,6 +92,47 @@ hpac_status check_io(const char *fn, const hpac_region_io *io, hpac::KArgs *a, h
   c->dtype = io->dtype;
   c->block = block;
   c->stream = (hipStream_t)io->stream;
+  return HPAC_OK;
+}
+
+// Binomial Options: the io description plus the tree.
+hpac_status check_bo(const char *fn, const hpac_region_io *io, int32_t steps, int32_t american, hpac::BoArgs *a,
+                     int *block) {
+  if (!io) return fail(HPAC_EINVAL, "%s: io is NULL", fn);
+  if (io->region != HPAC_REGION_BINOMIAL)
+    return fail(HPAC_EINVAL, "%s: region must be HPAC_REGION_BINOMIAL, got %d", fn, io->region);
+  if (io->dtype != HPAC_F32) return fail(HPAC_EUNSUPPORTED, "%s: the binomial region takes FP32 columns", fn);
+  if (io->n_in != 5 || io->n_out != 2) return fail(HPAC_EINVAL, "%s: the binomial region takes 5 inputs and 2 outputs", fn);
+  if (io->n < 0 || io->n > ((int64_t)1 << 31))
+    return fail(HPAC_EINVAL, "%s: n = %lld out of range [0, 2^31]", fn, (long long)io->n);
+  if (io->items_per_lane < 1 || io->items_per_lane > kMaxIpt)
+    return fail(HPAC_EINVAL, "%s: items_per_lane = %d out of range [1, %d]", fn, io->items_per_lane, kMaxIpt);
+  const int b = io->block_size == 0 ? 256 : io->block_size;
+  if (b < 64 || b > 256 || b % 64) return fail(HPAC_EINVAL, "%s: block_size = %d must be 64, 128, 192 or 256", fn, b);
+  if (steps < 1 || hpac::bo_nodes_per_lane(steps) == 0)
+    return fail(HPAC_EINVAL, "%s: steps = %d out of range [1, 1023]", fn, steps);
+  if (american != 0 && american != 1) return fail(HPAC_EINVAL, "%s: american must be 0 or 1", fn);
+  if (io->n > 0) {
+    if (!io->in || !io->out) return fail(HPAC_EINVAL, "%s: NULL column array", fn);
+    for (int j = 0; j < 5; ++j)
+      if (!io->in[j] || (uintptr_t)io->in[j] % 4) return fail(HPAC_EINVAL, "%s: input column %d is NULL or misaligned", fn, j);
+    for (int o = 0; o < 2; ++o)
+      if (!io->out[o] || (uintptr_t)io->out[o] % 4)
+        return fail(HPAC_EINVAL, "%s: output column %d is NULL or misaligned", fn, o);
+  }
+  if ((uintptr_t)io->trace % 4) return fail(HPAC_EINVAL, "%s: trace is not 4-byte aligned", fn);
+  if ((uintptr_t)io->counters % 8) return fail(HPAC_EINVAL, "%s: counters are not 8-byte aligned", fn);
+  *a = hpac::BoArgs{};
+  for (int j = 0; j < 5; ++j) a->in[j] = io->n > 0 ? (const float *)io->in[j] : nullptr;
+  for (int o = 0; o < 2; ++o) a->out[o] = io->n > 0 ? (float *)io->out[o] : nullptr;
+  a->n = io->n;
+  a->ipt = io->items_per_lane;
+  a->L = hpac::bo_units(io->n, io->items_per_lane);
+  a->steps = steps;
+  a->american = american != 0;
+  a->trace = io->trace;
+  a->counters = (unsigned long long *)io->counters;
+  *block = b;
   return HPAC_OK;
 }
 
@@ -318,6 +360,75 @@ hpac_status hpac_mlp_adam(const float *grad_partials, int64_t blocks, float *par
   a.bc1 = (float)(1.0 - pow((double)beta1, (double)step));
   a.bc2 = (float)(1.0 - pow((double)beta2, (double)step));
   return hip_status(fn, hpac::launch_mlp_adam(a, (hipStream_t)stream));
+}
+
+// ------------------------------------------------------------------ binomial
+
+int64_t hpac_bo_units(int64_t n, int32_t items_per_lane) {
+  if (n < 0 || n > ((int64_t)1 << 31) || items_per_lane < 1 || items_per_lane > kMaxIpt) return -1;
+  return hpac::bo_units(n, items_per_lane);
+}
+
+static hpac_status bo_launch(const char *fn, const hpac_region_io *io, const hpac::BoArgs &a, int tech, int block) {
+  if (a.n == 0) return HPAC_OK;
+  return hip_status(fn, hpac::launch_binomial(a, tech, block, (hipStream_t)io->stream));
+}
+
+hpac_status hpac_bo_exact(const hpac_region_io *io, int32_t steps, int32_t american) {
+  const char *fn = "hpac_bo_exact";
+  hpac::BoArgs a;
+  int block;
+  const hpac_status st = check_bo(fn, io, steps, american, &a, &block);
+  return st != HPAC_OK ? st : bo_launch(fn, io, a, 0, block);
+}
+
+hpac_status hpac_bo_iact(const hpac_region_io *io, int32_t steps, int32_t american, int32_t table_size,
+                         float threshold) {
+  const char *fn = "hpac_bo_iact";
+  hpac::BoArgs a;
+  int block;
+  hpac_status st = check_bo(fn, io, steps, american, &a, &block);
+  if (st == HPAC_OK) st = check_threshold(fn, threshold);
+  if (st != HPAC_OK) return st;
+  if (table_size < 1 || table_size > 32) return fail(HPAC_EINVAL, "%s: table_size = %d out of range [1, 32]", fn, table_size);
+  a.tsize = table_size;
+  a.threshold = threshold;
+  return bo_launch(fn, io, a, 1, block);
+}
+
+hpac_status hpac_bo_taf(const hpac_region_io *io, int32_t steps, int32_t american, int32_t history_size,
+                        int32_t prediction_size, float rsd_threshold) {
+  const char *fn = "hpac_bo_taf";
+  hpac::BoArgs a;
+  int block;
+  hpac_status st = check_bo(fn, io, steps, american, &a, &block);
+  if (st == HPAC_OK) st = check_threshold(fn, rsd_threshold);
+  if (st != HPAC_OK) return st;
+  if (history_size < 1 || history_size > 8)
+    return fail(HPAC_EINVAL, "%s: history_size = %d out of range [1, 8]", fn, history_size);
+  if (prediction_size < 1) return fail(HPAC_EINVAL, "%s: prediction_size = %d must be >= 1", fn, prediction_size);
+  a.hsize = history_size;
+  a.psize = prediction_size;
+  a.threshold = rsd_threshold;
+  return bo_launch(fn, io, a, 2, block);
+}
+
+hpac_status hpac_bo_perfo(const hpac_region_io *io, int32_t steps, int32_t american, int32_t kind, int32_t param,
+                          int32_t offset) {
+  const char *fn = "hpac_bo_perfo";
+  hpac::BoArgs a;
+  int block;
+  const hpac_status st = check_bo(fn, io, steps, american, &a, &block);
+  if (st != HPAC_OK) return st;
+  if (kind < HPAC_PERFO_SMALL || kind > HPAC_PERFO_FINI) return fail(HPAC_EINVAL, "%s: unknown kind %d", fn, kind);
+  if (param < 0) return fail(HPAC_EINVAL, "%s: param = %d must be >= 0", fn, param);
+  if ((kind == HPAC_PERFO_INI || kind == HPAC_PERFO_FINI) && param > 100)
+    return fail(HPAC_EINVAL, "%s: percentage %d out of range [0, 100]", fn, param);
+  if (offset < 0) return fail(HPAC_EINVAL, "%s: offset = %d must be >= 0", fn, offset);
+  a.kind = kind;
+  a.param = param;
+  a.offset = offset;
+  return bo_launch(fn, io, a, 3, block);
 }
 
 // ------------------------------------------------------------------ hydro

@@ -14,8 +14,9 @@ LIB_PATH = os.path.join(PKG, "libhpac.so")
 
 HPAC_OK, HPAC_EINVAL, HPAC_EUNSUPPORTED, HPAC_EHIP = 0, -1, -2, -3
 REGION_BS_PRICE, REGION_BS_PRICE_GRAD, REGION_BS_PRICE_F16, REGION_BS_PRICE_BF16 = 0, 1, 2, 3
+REGION_BINOMIAL = 4
 REGION_SHAPE = {REGION_BS_PRICE: (5, 2), REGION_BS_PRICE_GRAD: (5, 12), REGION_BS_PRICE_F16: (5, 2),
-                REGION_BS_PRICE_BF16: (5, 2)}
+                REGION_BS_PRICE_BF16: (5, 2), REGION_BINOMIAL: (5, 2)}
 F32, F16, BF16 = 0, 1, 2
 LEVEL_THREAD, LEVEL_WAVE, LEVEL_BLOCK = 0, 1, 2
 LEVELS = {"thread": LEVEL_THREAD, "wave": LEVEL_WAVE, "warp": LEVEL_WAVE, "block": LEVEL_BLOCK, "team": LEVEL_BLOCK}
@@ -124,6 +125,14 @@ def lib():
     L.hpac_hydro_init.restype = i32
     L.hpac_hydro_step.argtypes = [HP, HT, i32, HS, vp, vp, vp]
     L.hpac_hydro_step.restype = i32
+    L.hpac_bo_units.argtypes = [i64, i32]
+    L.hpac_bo_units.restype = i64
+    L.hpac_bo_exact.argtypes = [IO, i32, i32]
+    L.hpac_bo_iact.argtypes = [IO, i32, i32, i32, f32]
+    L.hpac_bo_taf.argtypes = [IO, i32, i32, i32, i32, f32]
+    L.hpac_bo_perfo.argtypes = [IO, i32, i32, i32, i32, i32]
+    for f in (L.hpac_bo_exact, L.hpac_bo_iact, L.hpac_bo_taf, L.hpac_bo_perfo):
+        f.restype = i32
     L.hpac_num_lanes.argtypes = [i64, i32]
     L.hpac_num_lanes.restype = i64
     L.hpac_trace_entries.argtypes = [i64, i32]
@@ -383,3 +392,37 @@ def hpac_hydro_step(params, tech, step, state, dec_eos=None, dec_hg=None, stream
     _call("hpac_hydro_step", lib().hpac_hydro_step(ctypes.byref(params), ctypes.byref(tech), int(step),
                                                    ctypes.byref(state), _addr(dec_eos), _addr(dec_hg),
                                                    _torch_stream(stream)))
+
+
+# ------------------------------------------------------------ binomial
+
+def hpac_bo_units(n, items_per_lane):
+    return lib().hpac_bo_units(n, items_per_lane)
+
+
+def _bo_io(inputs, outputs, kw):
+    kw = dict(kw)
+    kw["region"] = REGION_BINOMIAL
+    return make_io(inputs, outputs, **kw)
+
+
+def hpac_bo_exact(inputs, outputs, steps, american=True, **kw):
+    io = _bo_io(inputs, outputs, kw)
+    _call("hpac_bo_exact", lib().hpac_bo_exact(ctypes.byref(io), steps, int(american)))
+
+
+def hpac_bo_iact(inputs, outputs, steps, table_size, threshold, american=True, **kw):
+    io = _bo_io(inputs, outputs, kw)
+    _call("hpac_bo_iact", lib().hpac_bo_iact(ctypes.byref(io), steps, int(american), table_size, threshold))
+
+
+def hpac_bo_taf(inputs, outputs, steps, history_size, prediction_size, rsd_threshold, american=True, **kw):
+    io = _bo_io(inputs, outputs, kw)
+    _call("hpac_bo_taf", lib().hpac_bo_taf(ctypes.byref(io), steps, int(american), history_size, prediction_size,
+                                           rsd_threshold))
+
+
+def hpac_bo_perfo(inputs, outputs, steps, kind, param, offset=0, american=True, **kw):
+    io = _bo_io(inputs, outputs, kw)
+    k = PERFO_KINDS[kind] if isinstance(kind, str) else int(kind)
+    _call("hpac_bo_perfo", lib().hpac_bo_perfo(ctypes.byref(io), steps, int(american), k, param, offset))

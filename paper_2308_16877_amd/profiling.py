@@ -26,7 +26,7 @@ COPY_KERNEL = "k_copy"
 COPY_BYTES = 256 << 20
 # translation unit of each kernel family (by kernel-name prefix)
 KERNEL_UNITS = (("k_hydro", "hydro_kernels.hip"), ("k_mlp", "mlp_kernels.hip"), ("k_bs_", "greeks_kernels.hip"),
-                ("k_", "approx_kernels.hip"))
+                ("k_binomial", "binomial_kernels.hip"), ("k_", "approx_kernels.hip"))
 
 
 def _unit_files(unit):

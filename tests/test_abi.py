@@ -190,3 +190,38 @@ def test_invalid_hydro_arguments_are_rejected():
     expect(E, hstep, P, hydro_tech(eos_history=2, eos_prediction=2), 0, hydro_state(weos=0))
     expect(E, hstep, P, hydro_tech(hg_history=2, hg_prediction=2), 0, hydro_state(fhg=0))
     expect(E, hstep, P, hydro_tech(hg_history=2, hg_prediction=2), 0, hydro_state(z_hg=0))
+
+
+def bo_io(**kw):
+    args = dict(inputs=[FAKE] * 5, outputs=[FAKE] * 2, n=1000, items_per_lane=4, stream=0)
+    args.update(kw)
+    return args
+
+
+def test_invalid_binomial_arguments_are_rejected():
+    E = hpac.HPAC_EINVAL
+    assert hpac.hpac_bo_units(1000, 4) == 256 and hpac.hpac_bo_units(-1, 4) == -1
+    for steps in (0, 1024, -5):
+        expect(E, hpac.hpac_bo_exact, steps=steps, **bo_io())
+    expect(E, hpac.hpac_bo_exact, steps=64, american=2, **bo_io())
+    expect(E, hpac.hpac_bo_exact, steps=64, **bo_io(n=2 ** 31 + 1))
+    expect(E, hpac.hpac_bo_exact, steps=64, **bo_io(items_per_lane=0))
+    expect(E, hpac.hpac_bo_exact, steps=64, **bo_io(block_size=96))
+    expect(E, hpac.hpac_bo_exact, steps=64, **bo_io(inputs=[FAKE, FAKE, 0, FAKE, FAKE]))
+    expect(E, hpac.hpac_bo_exact, steps=64, **bo_io(outputs=[FAKE, FAKE + 2]))
+    expect(hpac.HPAC_EUNSUPPORTED, hpac.hpac_bo_exact, steps=64, **bo_io(dtype=hpac.F16))
+    for t in (0, 33):
+        expect(E, hpac.hpac_bo_iact, steps=64, table_size=t, threshold=0.1, **bo_io())
+    expect(E, hpac.hpac_bo_iact, steps=64, table_size=4, threshold=-1.0, **bo_io())
+    for h in (0, 9):
+        expect(E, hpac.hpac_bo_taf, steps=64, history_size=h, prediction_size=2, rsd_threshold=0.1, **bo_io())
+    expect(E, hpac.hpac_bo_taf, steps=64, history_size=2, prediction_size=0, rsd_threshold=0.1, **bo_io())
+    expect(E, hpac.hpac_bo_perfo, steps=64, kind=7, param=2, **bo_io())
+    expect(E, hpac.hpac_bo_perfo, steps=64, kind="ini", param=101, **bo_io())
+    expect(E, hpac.hpac_bo_perfo, steps=64, kind="small", param=2, offset=-1, **bo_io())
+    # the Black-Scholes entry points do not take the binomial region, nor the reverse
+    expect(E, hpac.hpac_exact, **io(region=hpac.REGION_BINOMIAL))
+    with pytest.raises(hpac.HpacError):
+        lib = hpac.lib()
+        desc = hpac.make_io([FAKE] * 5, [FAKE] * 2, n=10, region=hpac.REGION_BS_PRICE, stream=0)
+        hpac._call("hpac_bo_exact", lib.hpac_bo_exact(ctypes.byref(desc), 64, 1))
