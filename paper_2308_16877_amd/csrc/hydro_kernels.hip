@@ -36,46 +36,7 @@ namespace hpac {
 
 namespace {
 
-constexpr float kGauss = 0.577350269189625765f;  // 1/sqrt(3)
-
-struct DnTable {
-  float v[8][8][3];  // dN_c/dxi_j at Gauss point q: v[q][c][j]
-};
 constexpr float sgnf(int c, int d) { return ((c >> d) & 1) ? 1.0f : -1.0f; }
-constexpr DnTable make_dn() {
-  DnTable t{};
-  for (int q = 0; q < 8; ++q)
-    for (int c = 0; c < 8; ++c)
-      for (int j = 0; j < 3; ++j) {
-        float v = 0.125f * sgnf(c, j);
-        for (int l = 0; l < 3; ++l)
-          if (l != j) v *= 1.0f + sgnf(c, l) * sgnf(q, l) * kGauss;
-        t.v[q][c][j] = v;
-      }
-  return t;
-}
-
-// The 4 edges along direction j: lower corner of edge e.
-constexpr int edge_lo(int j, int e) {
-  // insert a zero bit at position j into the 2-bit number e
-  return j == 0 ? (e << 1) : j == 1 ? ((e & 2) << 1) | (e & 1) : e;
-}
-struct EdgeW {
-  float v[8][3][4];  // weight of edge e along j in J[.][j] at Gauss point q
-};
-constexpr EdgeW make_edge_w() {
-  EdgeW t{};
-  for (int q = 0; q < 8; ++q)
-    for (int j = 0; j < 3; ++j)
-      for (int e = 0; e < 4; ++e) {
-        const int c = edge_lo(j, e);
-        float v = 0.125f;
-        for (int l = 0; l < 3; ++l)
-          if (l != j) v *= 1.0f + sgnf(c, l) * sgnf(q, l) * kGauss;
-        t.v[q][j][e] = v;
-      }
-  return t;
-}
 
 // Hourglass base vectors: products of reference coordinates.
 constexpr float gamma_base(int a, int k) {
@@ -85,56 +46,97 @@ constexpr float gamma_base(int a, int k) {
                 : sgnf(k, 0) * sgnf(k, 1) * sgnf(k, 2);
 }
 
-// Volume (2x2x2 Gauss rule of det J) and, with kGrad, B = dV/dx.  J is
-// formed from edge differences, which neighbouring FP32 coordinates give
-// almost exactly, instead of from the coordinates themselves, whose
-// magnitude far exceeds an element's size.
+// Volume and, with kGrad, B = dV/dx of the trilinear hexahedron, in closed
+// form.  Writing the map in the Walsh-Hadamard basis of the corner signs,
+// x(xi) = a0 + a1 xi + a2 eta + a3 zeta + a4 xi eta + a5 xi zeta + a6 eta zeta
+// + a7 xi eta zeta with a_k = 1/8 sum_c h_k(c) x_c, and integrating det J
+// over the reference cube, the odd monomials vanish and
+//   V = 8 [a1, a2, a3] + 8/3 ([a1, a4, a5] + [a4, a2, a6] + [a5, a6, a3]),
+// [x, y, z] = x . (y cross z); a0 and a7 drop out.  Then dV/da_k = g_k (cross
+// products of the others) and B_c = 1/8 sum_k g_k h_k(c): two 8-point
+// Hadamard transforms and twelve cross products, about a quarter of the
+// Gauss-point work, and the same values (the Gauss rule is exact here).
+// The transform is taken of x_c - x_0, differences that neighbouring FP32
+// coordinates give almost exactly, since the coordinates themselves far
+// exceed an element's size.
+__device__ __forceinline__ void cross3(const float (&u)[3], const float (&v)[3], float (&w)[3]) {
+  w[0] = __builtin_fmaf(u[1], v[2], -u[2] * v[1]);
+  w[1] = __builtin_fmaf(u[2], v[0], -u[0] * v[2]);
+  w[2] = __builtin_fmaf(u[0], v[1], -u[1] * v[0]);
+}
+__device__ __forceinline__ float dot3(const float (&u)[3], const float (&v)[3]) {
+  return __builtin_fmaf(u[0], v[0], __builtin_fmaf(u[1], v[1], u[2] * v[2]));
+}
+
 template <bool kGrad>
 __device__ __forceinline__ float hex_volume(const float (&x)[8][3], float (&B)[8][3]) {
-  constexpr DnTable T = make_dn();
-  constexpr EdgeW EW = make_edge_w();
-  float D[3][4][3];
+  // A[m] = 8 a_m: Hadamard transform of the corner offsets; bit 0 of m is
+  // the xi factor, bit 1 eta, bit 2 zeta (a1 = A[1], a2 = A[2], a3 = A[4],
+  // a4 = A[3], a5 = A[5], a6 = A[6])
+  float A[8][3];
 #pragma unroll
-  for (int j = 0; j < 3; ++j)
+  for (int i = 0; i < 3; ++i) {
+    float d[8];
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
+    for (int c = 0; c < 8; ++c) d[c] = c ? x[c][i] - x[0][i] : 0.0f;
 #pragma unroll
-      for (int i = 0; i < 3; ++i) D[j][e][i] = x[edge_lo(j, e) | (1 << j)][i] - x[edge_lo(j, e)][i];
-  float V = 0.0f;
-  if (kGrad) {
-#pragma unroll
-    for (int c = 0; c < 8; ++c)
-#pragma unroll
-      for (int i = 0; i < 3; ++i) B[c][i] = 0.0f;
-  }
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    float J[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        float s = 0.0f;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) s = __builtin_fmaf(D[j][e][i], EW.v[q][j][e], s);
-        J[i][j] = s;
-      }
-    float cof[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
-        cof[i][j] = J[i1][j1] * J[i2][j2] - J[i1][j2] * J[i2][j1];
-      }
-    V += J[0][0] * cof[0][0] + J[0][1] * cof[0][1] + J[0][2] * cof[0][2];
-    if (kGrad) {
+    for (int j = 0; j < 3; ++j)
 #pragma unroll
       for (int c = 0; c < 8; ++c)
+        if (!((c >> j) & 1)) {
+          const float lo = d[c], hi = d[c | (1 << j)];
+          d[c] = lo + hi;
+          d[c | (1 << j)] = hi - lo;
+        }
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
+    for (int m = 0; m < 8; ++m) A[m][i] = d[m];
+  }
+  const float(&A1)[3] = A[1], (&A2)[3] = A[2], (&A3)[3] = A[4], (&A4)[3] = A[3], (&A5)[3] = A[5],
+               (&A6)[3] = A[6];
+  constexpr float kThird = 1.0f / 3.0f;
+  float x23[3], x45[3], x26[3], x63[3];
+  cross3(A2, A3, x23);
+  cross3(A4, A5, x45);
+  cross3(A2, A6, x26);
+  cross3(A6, A3, x63);
+  // G1 = A2 x A3 + (A4 x A5) / 3 = 64 dV/dA1 (times 8 a1 . G1 it gives the leading terms)
+  float G1[3];
 #pragma unroll
-          for (int j = 0; j < 3; ++j) B[c][i] = __builtin_fmaf(cof[i][j], T.v[q][c][j], B[c][i]);
+  for (int i = 0; i < 3; ++i) G1[i] = __builtin_fmaf(x45[i], kThird, x23[i]);
+  const float V = (dot3(A1, G1) + (dot3(A4, x26) + dot3(A5, x63)) * kThird) * (1.0f / 64.0f);
+  if (kGrad) {
+    float x31[3], x64[3], x12[3], x56[3], x51[3], x14[3], x42[3], x35[3];
+    cross3(A3, A1, x31);
+    cross3(A6, A4, x64);
+    cross3(A1, A2, x12);
+    cross3(A5, A6, x56);
+    cross3(A5, A1, x51);
+    cross3(A1, A4, x14);
+    cross3(A4, A2, x42);
+    cross3(A3, A5, x35);
+    // E[m] = 64 dV/dA_m at the Hadamard position m, then the inverse transform
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      float E[8];
+      E[0] = 0.0f;
+      E[7] = 0.0f;
+      E[1] = G1[i];
+      E[2] = __builtin_fmaf(x64[i], kThird, x31[i]);
+      E[4] = __builtin_fmaf(x56[i], kThird, x12[i]);
+      E[3] = (x51[i] + x26[i]) * kThird;
+      E[5] = (x14[i] + x63[i]) * kThird;
+      E[6] = (x42[i] + x35[i]) * kThird;
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+          if (!((m >> j) & 1)) {
+            const float u = E[m], v = E[m | (1 << j)];
+            E[m] = u - v;
+            E[m | (1 << j)] = u + v;
+          }
+#pragma unroll
+      for (int c = 0; c < 8; ++c) B[c][i] = E[c] * (1.0f / 64.0f);
     }
   }
   return V;
