@@ -84,6 +84,17 @@ def pmc_probe(torch, hpac, x_copies, n):
     # three exact steps of the 90^3 blast
     h = Hydro(90)
     h.run(3)
+    del h
+    # the Binomial Options techniques on the structured variant of their leg
+    from paper_2308_16877_amd import inputs
+    n_bo = 65536
+    xb = [torch.from_numpy(c).to(dev) for c in inputs.periodic(n_bo, hpac.hpac_bo_units(n_bo, 16), jitter=1e-3)]
+    ob = [torch.zeros(n_bo, dtype=torch.float32, device=dev) for _ in range(2)]
+    for r in range(3):
+        for fn, ipt, params in BO_TECHS.values():
+            f = {"exact": hpac.hpac_bo_exact, "iact": hpac.hpac_bo_iact, "taf": hpac.hpac_bo_taf,
+                 "perfo": hpac.hpac_bo_perfo}[fn]
+            f(xb, ob, 512, items_per_lane=ipt, **params)
     torch.cuda.synchronize()
     print(json.dumps({"pmc_probe": "done", "n": n, "copy_bytes": COPY_PROBE_BYTES}), flush=True)
 

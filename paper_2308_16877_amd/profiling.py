@@ -129,7 +129,11 @@ def traffic_summary(fetch_csv, write_csv, kernel_sub, workload, out_json, fetch_
 
 
 def _kernel_match(name, sub):
+    """sub names a kernel (every instantiation of it) or, ending in a
+    template-argument prefix such as "k_binomial<9, 1", some of them."""
     base = short_name(name)
+    if "<" in sub:
+        return base.startswith("hpac::" + sub)
     return base.startswith("hpac::" + sub + "<") or base == "hpac::" + sub
 
 
