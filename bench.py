@@ -13,7 +13,8 @@ Prints one JSON line: whole-step region items/s, per-technique items/s,
 speedup over the exact kernel and MAPE against the exact kernel's outputs,
 the roofline of the dominant kernel (HIP-event durations on the launch
 stream), and the CPU oracle timed on a bounded sample.  Further legs, each
-at its own accuracy: the Greeks adjoint, the reduced-precision variants,
+at its own accuracy: the technique-parameter grid on the same options (its
+fastest point within 0.5% MAPE), the Greeks adjoint, the reduced-precision variants,
 the decision hierarchy and items-per-lane study, the Binomial Options
 workload, the MLP surrogate and the Sedov hydro under TAF and perforation.
 """
@@ -330,15 +331,59 @@ def technique_point(torch, hpac, x_copies, n, fn, ipt, params, exact_out, steps=
     dev = x_copies[0][0].device
     out = [torch.zeros(n, dtype=torch.float32, device=dev) for _ in range(2)]
     stream = torch.cuda.current_stream()
-    preps = [hpac.prepare(fn, xs, out, items_per_lane=ipt, block_size=256, stream=stream, **params)
+    params = dict(params)
+    block = params.pop("block_size", 256)
+    preps = [hpac.prepare(fn, xs, out, items_per_lane=ipt, block_size=block, stream=stream, **params)
              for xs in x_copies]
     t = time_pairs(torch, {"p": preps}, steps, 1)["p"] / len(preps)
     cnt = torch.zeros(hpac.NUM_COUNTERS, dtype=torch.int64, device=dev)
     {"exact": hpac.hpac_exact, "iact": hpac.hpac_iact, "taf": hpac.hpac_taf, "perfo": hpac.hpac_perfo}[fn](
-        x_copies[0], out, items_per_lane=ipt, block_size=256, counters=cnt, **params)
+        x_copies[0], out, items_per_lane=ipt, block_size=block, counters=cnt, **params)
     torch.cuda.synchronize()
     c = cnt.cpu().tolist()
     return {"ms": t, "approx_frac": c[1] / max(c[0], 1), "mape": mape_torch(torch, exact_out, out)}
+
+
+SWEEP = {
+    # technique: (items per lane, parameter grid)
+    "iact": (16, [dict(table_size=t, threshold=th, tables_per_wave=1, level="wave")
+                  for t in (4, 8, 16, 32) for th in (0.01, 0.05, 0.1)]),
+    "taf": (16, [dict(history_size=h, prediction_size=h, rsd_threshold=th, level="wave")
+                 for h in (2, 4, 8) for th in (0.001, 0.01, 0.1)]),
+    "perfo": (20, [dict(kind="small", param=m, offset=0) for m in (10, 5, 2)]),
+}
+
+
+def sweep_leg(torch, hpac, x_copies, n):
+    """The parameter grid of the 2^24-option workload: iACT tables
+    {4, 8, 16, 32} x thresholds {0.01, 0.05, 0.1}, TAF windows {2, 4, 8} x RSD
+    {0.001, 0.01, 0.1} (prediction size = window), small perforation at 10,
+    20 and 50% (M = 10, 5, 2).  Per point: ms per launch, speedup over the
+    exact kernel, approximated fraction and MAPE; and the fastest point within
+    the 0.5% MAPE bar."""
+    dev = x_copies[0][0].device
+    ex = [torch.zeros(n, dtype=torch.float32, device=dev) for _ in range(2)]
+    hpac.hpac_exact(x_copies[0], ex, items_per_lane=1)
+    # the exact kernel's launch shapes; speedups are against the fastest
+    exact = {}
+    for ipt in (1, 2, 4, 8, 16):
+        for block in (128, 256):
+            exact["ipt%d_block%d" % (ipt, block)] = technique_point(torch, hpac, x_copies, n, "exact", ipt,
+                                                                    dict(block_size=block), ex)["ms"]
+    best_exact = min(exact, key=exact.get)
+    exact_ms = exact[best_exact]
+    points = []
+    grid = [(tech, ipt, params) for tech, (ipt, g) in SWEEP.items() for params in g]
+    # items per lane of the memoization techniques at their headline parameters
+    grid += [(tech, ipt, dict(TECHS[tech][2])) for tech in ("iact", "taf") for ipt in (4, 64, 256)]
+    for tech, ipt, params in grid:
+        r = technique_point(torch, hpac, x_copies, n, tech, ipt, params, ex)
+        r.update(technique=tech, items_per_lane=ipt, params=params, speedup_vs_exact=exact_ms / r["ms"])
+        points.append(r)
+    ok = [p for p in points if p["mape"] <= MAPE_BAR]
+    best = max(ok, key=lambda p: p["speedup_vs_exact"]) if ok else None
+    return {"exact_ms_by_shape": exact, "best_exact": best_exact, "exact_ms": exact_ms, "points": points,
+            "best_at_mape_0.005": best}
 
 
 def hierarchy_and_ipt_leg(torch, hpac, n):
@@ -464,8 +509,59 @@ def hydro_leg(torch, n=90, steps=500):
                      "qoi_err_vs_fp64_oracle": abs(q / ref64 - 1) if ref64 else None,
                      "total_energy": ie + ke, "time": h.time()}
         del h
+    sweep = hydro_sweep(torch, res["exact"]["ms_per_step"], res["exact"]["origin_energy"], ref64, n, steps)
     return {"workload": "Sedov blast, %d^3 elements, %d steps, FP32 state, FP64 dt" % (n, steps),
-            "fp64_oracle_origin_energy": ref64, "techniques": res}
+            "fp64_oracle_origin_energy": ref64, "techniques": res, "sweep": sweep}
+
+
+HYDRO_SWEEP = (
+    # TAF on each region at wave and thread level over the grid of the
+    # 2^24-option workload (prediction = window), and hourglass perforation
+    # at 10, 20 and 50%
+    [("%s_taf_%s_h%d_%g" % (region, level, h, th), {region: (h, h, th, level)})
+     for region in ("eos", "hg") for level in ("wave", "thread") for h in (2, 4, 8) for th in (0.001, 0.01, 0.1)]
+    + [("hg_perfo_small_M%d" % m, dict(perfo=("small", m, 1))) for m in (10, 5, 2)])
+
+
+def hydro_sweep(torch, exact_ms_per_step, exact_q, ref64, n=90, steps=500):
+    """Each point of HYDRO_SWEEP over the whole run: ms per step, speedup,
+    QoI error against the exact GPU run and the FP64 oracle's run, and the
+    fraction of (wave, step) decisions that approximated each region (a
+    second, recorded run of the same deterministic trajectory)."""
+    from paper_2308_16877_amd.hydro import Hydro, Tech
+    pts = {}
+    for name, kw in HYDRO_SWEEP:
+        h = Hydro(n, tech=Tech(**kw))
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        h.run(steps)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        q = h.origin_energy()
+        del h
+        frac = {}
+        if "eos" in kw or "hg" in kw:
+            region = "eos" if "eos" in kw else "hg"
+            h = Hydro(n, tech=Tech(**kw))
+            groups = h.W if kw[region][3] == "wave" else h.E
+            acc = torch.zeros((), dtype=torch.int64, device="cuda:0")
+            for _ in range(steps):
+                h.step(record=True)
+                acc += getattr(h, "dec_" + region)[:groups].sum()
+            frac = {region: int(acc) / (groups * steps)}
+            del h
+        else:
+            frac = {"hg": 1.0 / kw["perfo"][1]}
+        pts[name] = {"ms_per_step": ms, "speedup_vs_exact": exact_ms_per_step / ms,
+                     "qoi_err_vs_exact_gpu": abs(q / exact_q - 1),
+                     "qoi_err_vs_fp64_oracle": abs(q / ref64 - 1) if ref64 else None,
+                     "approx_frac": frac}
+    ok = {k: v for k, v in pts.items() if v["qoi_err_vs_exact_gpu"] <= MAPE_BAR}
+    best = max(ok, key=lambda k: ok[k]["speedup_vs_exact"]) if ok else None
+    return {"points": pts, "best_at_qoi_err_0.005": {"technique": best, **ok[best]} if best else None}
 
 
 def hydro_cpu_baseline(steps=6, n=90):
@@ -597,6 +693,11 @@ def main():
             structured["best_at_mape_0.005"] = {"variant": v, "technique": t,
                                                 "speedup_vs_exact": r["speedup_vs_exact"], "mape": r["mape"]}
 
+    sweep = None
+    if not args.no_structured:
+        print("[bench] parameter sweep", file=sys.stderr, flush=True)
+        sweep = sweep_leg(torch, hpac, x_copies, n)
+
     greeks = None
     if not args.no_structured:
         print("[bench] greeks", file=sys.stderr, flush=True)
@@ -646,6 +747,7 @@ def main():
                                "mape": ok[best]["mape"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "parameter_sweep": sweep,
         "structured_locality": structured,
         "greeks": greeks,
         "precision": precision,

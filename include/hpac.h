@@ -261,14 +261,14 @@ hpac_status hpac_mlp_adam(const float *grad_partials, int64_t blocks, float *par
  * state persists in the caller's buffers between calls):
  *  - hourglass region (24 corner forces, added to the element's corner
  *    forces): TAF (history 1..8; an approximated element adds its last
- *    accurate forces, fhg) or herded perforation (section 3.1.5) of the
+ *    accurate forces, the newest slot of its window) or herded perforation (section 3.1.5) of the
  *    element loop at perfo_items_per_lane, offset = timestep (a skipped
  *    iteration adds nothing);
  *  - EOS region (e, p, q, c): TAF; approximated elements keep their values.
  * TAF decides per wave (majority of its 64 elements) or per element (thread
  * level), the two finest levels of section 3.1.2.
  * Layouts: element fields n^3 floats, element z = i + n (j + n k); node
- * fields (n+1)^3 floats, node i + (n+1) (j + (n+1) k); force and fhg are
+ * fields (n+1)^3 floats, node i + (n+1) (j + (n+1) k); force is
  * [(corner * 3 + dim) * n^3 + z] with corner a + 2b + 4c for node
  * (i+a, j+b, k+c); windows are [(slot * outputs + o) * n^3 + z];
  * per-group ints have hpac_hydro_groups(n, level) entries.  All device memory, owned
@@ -293,7 +293,6 @@ typedef struct hpac_hydro_state {
   float *e, *p, *q, *c;         /* element specific energy, pressure, viscosity, sound speed */
   float *vol, *mass;            /* element volume at the last force evaluation, mass */
   float *force;                 /* corner forces, 24 n^3 */
-  float *fhg;                   /* last hourglass forces, 24 n^3 (hourglass TAF only) */
   float *weos;                  /* EOS window, eos_history * 4 n^3 (EOS TAF only) */
   int32_t *rho_eos, *z_eos;     /* per decision group: countdown, pushes (EOS TAF only) */
   float *whg;                   /* hourglass window, hg_history * 24 n^3 (hourglass TAF only) */
@@ -321,9 +320,9 @@ int64_t hpac_hydro_waves(int32_t n);
 int64_t hpac_hydro_groups(int32_t n, int32_t level);
 int64_t hpac_hydro_partials(int32_t n);
 
-/* Initial state (every non-NULL field of *state is written; fhg is zeroed if
- * given, and rho_* / z_* are zeroed over hpac_hydro_groups(n, THREAD)
- * entries, so they must have that many when given). */
+/* Initial state (every non-NULL field of *state is written; rho_* / z_* are
+ * zeroed over hpac_hydro_groups(n, THREAD) entries, so they must have that
+ * many when given; windows are only read after they are written). */
 hpac_status hpac_hydro_init(const hpac_hydro_params *params, double e_origin, const hpac_hydro_state *state,
                             void *stream);
 

@@ -488,7 +488,6 @@ static hpac::HydroArgs hydro_args(const hpac_hydro_params *P, const hpac_hydro_s
   a.vol = S->vol;
   a.mass = S->mass;
   a.force = S->force;
-  a.fhg = S->fhg;
   a.weos = S->weos;
   a.rho_eos = S->rho_eos;
   a.z_eos = S->z_eos;
@@ -528,7 +527,7 @@ hpac_status hpac_hydro_init(const hpac_hydro_params *params, double e_origin, co
   if (!isfinite(e_origin) || e_origin < 0) return fail(HPAC_EINVAL, "%s: e_origin must be finite and >= 0", fn);
   if ((state->rho_eos == NULL) != (state->z_eos == NULL) || (state->rho_hg == NULL) != (state->z_hg == NULL))
     return fail(HPAC_EINVAL, "%s: a countdown array without its push-count array", fn);
-  if ((state->fhg && !aligned4(state->fhg)) || (state->rho_eos && !aligned4(state->rho_eos)) ||
+  if ((state->rho_eos && !aligned4(state->rho_eos)) ||
       (state->z_eos && !aligned4(state->z_eos)) || (state->rho_hg && !aligned4(state->rho_hg)) ||
       (state->z_hg && !aligned4(state->z_hg)))
     return fail(HPAC_EINVAL, "%s: misaligned optional field", fn);
@@ -566,7 +565,6 @@ hpac_status hpac_hydro_step(const hpac_hydro_params *params, const hpac_hydro_te
     return fail(HPAC_EINVAL, "%s: EOS TAF needs weos, rho_eos and z_eos", fn);
   if (T.hg_history && (!aligned4(state->whg) || !aligned4(state->rho_hg) || !aligned4(state->z_hg)))
     return fail(HPAC_EINVAL, "%s: hourglass TAF needs whg, rho_hg and z_hg", fn);
-  if (T.hg_history && !aligned4(state->fhg)) return fail(HPAC_EINVAL, "%s: hourglass TAF needs fhg", fn);
   hpac::HydroArgs a = hydro_args(params, state);
   a.step = step;
   a.dec_eos = T.eos_history ? dec_eos : nullptr;

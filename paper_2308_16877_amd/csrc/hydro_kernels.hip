@@ -9,8 +9,8 @@
 //   n^3 elements on [0, side]^3, (n+1)^3 nodes, symmetry planes x=0, y=0,
 //   z=0, free outer faces.  Element (i,j,k), corner a + 2b + 4c is node
 //   (i+a, j+b, k+c); reference coordinates s = (2a-1, 2b-1, 2c-1).
-//   k_hydro_force  per element: volume V and its gradient B = dV/dx from the
-//                  2x2x2 Gauss rule (exact for a trilinear hexahedron);
+//   k_hydro_force  per element: volume V and its gradient B = dV/dx in
+//                  closed form (exact for a trilinear hexahedron);
 //                  corner forces (p + q) B + hourglass forces (viscous
 //                  Flanagan-Belytschko form); the element's FP64 time-step
 //                  bound, reduced per workgroup.
@@ -27,8 +27,9 @@
 // and push count of each wave are one int each, read by the whole wave and
 // written by its first lane; at thread level every element has its own.
 // An approximate EOS step reads only the countdown; an approximate
-// hourglass step adds the last accurate hourglass forces instead of
-// computing them.  A perforated hourglass iteration adds nothing.
+// hourglass step adds the last accurate hourglass forces -- the newest slot
+// of its window -- instead of computing them.  A perforated hourglass
+// iteration adds nothing.
 #include "launch_hydro.hpp"
 #include "wave.hpp"
 
@@ -206,25 +207,51 @@ __device__ __forceinline__ void gather3(const float *const *src, const ElemIdx &
   }
 }
 
-// Whether the RSD of every output over the h window slots is below theta:
-// slot `fresh` holds y (not yet visible in memory), the others are read from
-// the window.  Division-free, in FP64 (see rsd_below in approx_kernels.hip).
-template <int NO>
+// Whether the RSD of every output over the h window slots is below theta.
+// The value y in slot `fresh`, just pushed by this thread, is read back as
+// a pivot.  With the deviations d_q = w_q - y of the other slots (exact in
+// FP64 for FP32 data), s' = sum d_q and Q = sum d_q^2, the two-pass
+// statistic is
+//   D = sum_q (h w_q - s)^2 = h (h Q - s'^2),   s = sum_q w_q = h y + s',
+// shifted by a sample so that it does not cancel (h Q >= s'^2 by
+// Cauchy-Schwarz, so D >= 0).  Division-free test D < h theta^2 s^2, and D
+// == 0 (a constant window) passes whenever theta > 0, as in the
+// Black-Scholes TAF.  Outputs go in groups of G, a slot of a whole group per
+// memory round trip; the first failing group decides.
+template <int NO, int G>
 __device__ __forceinline__ bool window_rsd_below(const float *win, int64_t E, int64_t z, int h, int fresh,
-                                                 const float (&y)[NO], double th2, bool th_pos) {
-  bool ok = true;
+                                                 double th2, bool th_pos) {
+  static_assert(NO % G == 0, "outputs come in whole groups");
+  for (int o0 = 0; o0 < NO; o0 += G) {
+    double y[G], s1[G], Q[G];
 #pragma unroll
-  for (int o = 0; o < NO; ++o) {
-    double s = 0.0;
-    for (int q = 0; q < h; ++q) s += (double)(q == fresh ? y[o] : win[((int64_t)q * NO + o) * E + z]);
-    double D = 0.0;
-    for (int q = 0; q < h; ++q) {
-      const double d = (double)h * (double)(q == fresh ? y[o] : win[((int64_t)q * NO + o) * E + z]) - s;
-      D = __builtin_fma(d, d, D);
+    for (int g = 0; g < G; ++g) {
+      y[g] = (double)win[((int64_t)fresh * NO + o0 + g) * E + z];
+      s1[g] = 0.0;
+      Q[g] = 0.0;
     }
-    ok = ok && (D == 0.0 ? th_pos : D < (double)h * th2 * (s * s));
+    for (int q = 0; q < h; ++q) {
+      if (q == fresh) continue;
+      float wq[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) wq[g] = win[((int64_t)q * NO + o0 + g) * E + z];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const double d = (double)wq[g] - y[g];
+        s1[g] += d;
+        Q[g] = __builtin_fma(d, d, Q[g]);
+      }
+    }
+    bool ok = true;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const double D = (double)h * __builtin_fma((double)h, Q[g], -(s1[g] * s1[g]));
+      const double sum = __builtin_fma((double)h, y[g], s1[g]);
+      ok = ok && (D == 0.0 ? th_pos : D < (double)h * th2 * (sum * sum));
+    }
+    if (!ok) return false;
   }
-  return ok;
+  return true;
 }
 
 __device__ __forceinline__ double block_min(double v, double *red) {
@@ -263,8 +290,6 @@ __global__ void __launch_bounds__(256) k_hydro_init_elem(HydroArgs a, double e_o
   a.p[z] = p;
   a.q[z] = 0.0f;
   a.c[z] = sqrtf(a.gamma * fmaxf(p, 0.0f) / rho0);
-  if (a.fhg)
-    for (int o = 0; o < 24; ++o) a.fhg[o * a.E + z] = 0.0f;
 }
 
 __global__ void __launch_bounds__(256) k_hydro_init_node(HydroArgs a) {
@@ -303,6 +328,15 @@ __global__ void __launch_bounds__(256) k_hydro_init_groups(HydroArgs a, double d
 
 // ------------------------------------------------------------------ force
 
+// Corner forces (p + q) B + f of one element, f = NULL for none.
+__device__ __forceinline__ void store_forces(float *force, int64_t E, int64_t z, float pq, const float (&B)[8][3],
+                                             const float (*f)[3]) {
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) force[(c * 3 + d) * E + z] = f ? __builtin_fmaf(pq, B[c][d], f[c][d]) : pq * B[c][d];
+}
+
 template <int HG>
 __global__ void __launch_bounds__(256) k_hydro_force(HydroArgs a) {
   __shared__ double red[256];
@@ -310,13 +344,13 @@ __global__ void __launch_bounds__(256) k_hydro_force(HydroArgs a) {
   const int64_t E = a.E;
   const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = lane_id();
+  constexpr bool kTaf = HG == kHgTafWave || HG == kHgTafThread;
   double bound = INFINITY;
   for (int k = 0; k < a.hg_ipt; ++k) {
     const int64_t z = l + (int64_t)k * a.hg_L;
     const bool active = z < E;
     const int64_t w = l >> 6;  // TAF: one element per lane
-    constexpr bool kTaf = HG == kHgTafWave || HG == kHgTafThread;
-    bool compute_hg = true;
+    bool compute_hg = HG != kHgNone;
     int rho = 0, pushes = 0;
     if (HG == kHgPerfo) {
       const int M = a.perfo_param;
@@ -342,52 +376,48 @@ __global__ void __launch_bounds__(256) k_hydro_force(HydroArgs a) {
     bool crit = false, voted = false;
     if (active) {
       const ElemIdx ei(z, n);
-      float x[8][3], u[8][3], B[8][3], f[8][3];
+      float x[8][3], u[8][3], B[8][3];
       gather3(a.x, ei, n, x);
       gather3(a.u, ei, n, u);
       const float V = hex_volume<true>(x, B);
       a.vol[z] = V;
-      const float rho_e = a.mass[z] / V;
-      if (compute_hg) {
-        hourglass(x, u, B, V, rho_e, a.c[z], a.khg, f);
-        if (kTaf)
-#pragma unroll
-          for (int o = 0; o < 24; ++o) a.fhg[o * E + z] = f[o / 3][o % 3];
-      } else if (kTaf) {  // TAF's approximate path: the last accurate forces
-#pragma unroll
-        for (int o = 0; o < 24; ++o) f[o / 3][o % 3] = a.fhg[o * E + z];
-      } else {  // a perforated iteration adds no hourglass force
-#pragma unroll
-        for (int o = 0; o < 24; ++o) f[o / 3][o % 3] = 0.0f;
-      }
       const float pq = a.p[z] + a.q[z];
+      // volume rate sum B . u (B sums to zero, so relative to corner 0)
       float vdot = 0.0f;
 #pragma unroll
-      for (int c = 0; c < 8; ++c)
+      for (int c = 1; c < 8; ++c)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          a.force[(c * 3 + d) * E + z] = __builtin_fmaf(pq, B[c][d], f[c][d]);
-          if (c > 0) vdot = __builtin_fmaf(B[c][d], u[c][d] - u[0][d], vdot);
+        for (int d = 0; d < 3; ++d) vdot = __builtin_fmaf(B[c][d], u[c][d] - u[0][d], vdot);
+      if (compute_hg) {
+        float f[8][3];
+        hourglass(x, u, B, V, a.mass[z] / V, a.c[z], a.khg, f);
+        store_forces(a.force, E, z, pq, B, f);
+        if (kTaf) {  // push the accurate forces
+          const int slot = pushes % a.hg_h;
+#pragma unroll
+          for (int o = 0; o < 24; ++o) a.whg[((int64_t)slot * 24 + o) * E + z] = f[o / 3][o % 3];
         }
+      } else if (kTaf) {
+        // TAF's approximate path: the newest window slot holds the last
+        // accurate forces (a countdown is only set after a push)
+        const int slot = (pushes - 1) % a.hg_h;
+        float f[8][3];
+#pragma unroll
+        for (int o = 0; o < 24; ++o) f[o / 3][o % 3] = a.whg[((int64_t)slot * 24 + o) * E + z];
+        store_forces(a.force, E, z, pq, B, f);
+      } else {
+        store_forces(a.force, E, z, pq, B, nullptr);  // perforated: no hourglass force
+      }
       // time-step bound in FP64
       const double Vd = (double)V, rd = (double)a.mass[z] / Vd;
       const double ceff2 = a.gamma_d * fmax((double)pq, 0.0) / rd;
       double b = ceff2 > 0.0 ? a.cfl * cbrt(Vd) / sqrt(ceff2) : INFINITY;
       if (vdot != 0.0f) b = fmin(b, a.dvmax * Vd / fabs((double)vdot));
       bound = fmin(bound, b);
-      if (kTaf && compute_hg) {
-        const int slot = pushes % a.hg_h;
-        float y[24];
-#pragma unroll
-        for (int o = 0; o < 24; ++o) {
-          y[o] = f[o / 3][o % 3];
-          a.whg[((int64_t)slot * 24 + o) * E + z] = y[o];
-        }
-        if (pushes + 1 >= a.hg_h) {
-          voted = true;
-          const double th = (double)a.hg_theta;
-          crit = window_rsd_below<24>(a.whg, E, z, a.hg_h, slot, y, th * th, th > 0.0);
-        }
+      if (kTaf && compute_hg && pushes + 1 >= a.hg_h) {  // the window is full: vote
+        voted = true;
+        const double th = (double)a.hg_theta;
+        crit = window_rsd_below<24, 8>(a.whg, E, z, a.hg_h, pushes % a.hg_h, th * th, th > 0.0);
       }
     }
     if (HG == kHgTafThread && active) {
@@ -537,7 +567,7 @@ __global__ void __launch_bounds__(256) k_hydro_eos(HydroArgs a) {
       if (pushes + 1 >= a.eos_h) {
         voted = true;
         const double th = (double)a.eos_theta;
-        crit = window_rsd_below<4>(a.weos, E, z, a.eos_h, slot, y, th * th, th > 0.0);
+        crit = window_rsd_below<4, 4>(a.weos, E, z, a.eos_h, slot, th * th, th > 0.0);
       }
     }
   }
@@ -573,10 +603,17 @@ hipError_t launch_hydro_init(const HydroArgs &a, double e_origin, double dt0, hi
 
 hipError_t launch_hydro_step(const HydroArgs &a, int hg_mode, int eos_mode, hipStream_t s) {
   const unsigned fblocks = (unsigned)((a.hg_L + 255) / 256);
+  if (hg_mode == kHgPerfo && a.hg_ipt == 1 && a.perfo_param > 0 && (a.perfo_kind == 0 || a.perfo_kind == 1)) {
+    // one item per lane: the herded rule keeps or drops the whole step
+    const int r = (int)((int64_t)a.step % a.perfo_param);
+    const bool keep = a.perfo_kind == 0 ? r != a.perfo_param - 1 : r == 0;
+    hg_mode = keep ? kHgExact : kHgNone;
+  }
   switch (hg_mode) {
     case kHgExact: hipLaunchKernelGGL(k_hydro_force<kHgExact>, dim3(fblocks), dim3(256), 0, s, a); break;
     case kHgTafWave: hipLaunchKernelGGL(k_hydro_force<kHgTafWave>, dim3(fblocks), dim3(256), 0, s, a); break;
     case kHgTafThread: hipLaunchKernelGGL(k_hydro_force<kHgTafThread>, dim3(fblocks), dim3(256), 0, s, a); break;
+    case kHgNone: hipLaunchKernelGGL(k_hydro_force<kHgNone>, dim3(fblocks), dim3(256), 0, s, a); break;
     default: hipLaunchKernelGGL(k_hydro_force<kHgPerfo>, dim3(fblocks), dim3(256), 0, s, a); break;
   }
   hipLaunchKernelGGL(k_hydro_dt, dim3(1), dim3(256), 0, s, a, (int64_t)fblocks);

@@ -5,8 +5,9 @@
 
 namespace hpac {
 
-// Lagrangian hydro (hydro_kernels.hip).  Region modes:
-constexpr int kHgExact = 0, kHgTafWave = 1, kHgTafThread = 2, kHgPerfo = 3;
+// Lagrangian hydro (hydro_kernels.hip).  Region modes (kHgNone: no
+// hourglass force, a step that herded perforation drops as a whole):
+constexpr int kHgExact = 0, kHgTafWave = 1, kHgTafThread = 2, kHgPerfo = 3, kHgNone = 4;
 constexpr int kEosExact = 0, kEosTafWave = 1, kEosTafThread = 2;
 
 struct HydroArgs {
@@ -16,7 +17,7 @@ struct HydroArgs {
   float gamma, cq, cl, khg;
   double gamma_d, cfl, growth, dvmax;
   float *x[3], *u[3], *un[3];
-  float *mnode, *e, *p, *q, *c, *vol, *mass, *force, *fhg;
+  float *mnode, *e, *p, *q, *c, *vol, *mass, *force;
   float *weos;
   int32_t *rho_eos, *z_eos;
   float *whg;

@@ -68,7 +68,7 @@ class hpac_hydro_params(ctypes.Structure):
 
 class hpac_hydro_state(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p * 3), ("u", ctypes.c_void_p * 3), ("unew", ctypes.c_void_p * 3)] + \
-               [(f, ctypes.c_void_p) for f in ("mnode", "e", "p", "q", "c", "vol", "mass", "force", "fhg", "weos",
+               [(f, ctypes.c_void_p) for f in ("mnode", "e", "p", "q", "c", "vol", "mass", "force", "weos",
                                                 "rho_eos", "z_eos", "whg", "rho_hg", "z_hg", "clock",
                                                 "dt_partials")]
 

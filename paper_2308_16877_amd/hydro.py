@@ -44,7 +44,7 @@ class Tech:
 
 
 class Hydro:
-    FIELDS = ("mnode", "e", "p", "q", "c", "vol", "mass", "force", "fhg")
+    FIELDS = ("mnode", "e", "p", "q", "c", "vol", "mass", "force")
 
     def __init__(self, n, e_origin=None, tech=None, device="cuda:0", **par):
         self.n = int(n)
@@ -62,7 +62,6 @@ class Hydro:
             setattr(self, f, torch.zeros(E, **f32))
         self.force = torch.zeros(24, E, **f32)
         t = self.tech
-        self.fhg = torch.zeros(24, E, **f32) if t.hg else None
         i32 = dict(dtype=torch.int32, device=device)
         # decision-group state: one entry per element covers both levels
         self.weos = torch.zeros(max(t.eos[0], 1) * 4, E, **f32) if t.eos else None
@@ -122,7 +121,7 @@ class Hydro:
     def numpy_state(self):
         """Host copy of the state (float64 arrays) in the oracle's layout."""
         out = {}
-        for f in ("x", "u", "mnode", "e", "p", "q", "c", "vol", "mass", "force", "fhg", "weos", "whg"):
+        for f in ("x", "u", "mnode", "e", "p", "q", "c", "vol", "mass", "force", "weos", "whg"):
             t = getattr(self, f)
             out[f] = t.double().cpu().numpy() if t is not None else None
         for f in ("rho_eos", "z_eos", "rho_hg", "z_hg"):

@@ -126,7 +126,7 @@ def hydro_state(**over):
         s.x[d] = FAKE
         s.u[d] = FAKE
         s.unew[d] = FAKE
-    for f in ("mnode", "e", "p", "q", "c", "vol", "mass", "force", "fhg", "weos", "rho_eos", "z_eos", "whg",
+    for f in ("mnode", "e", "p", "q", "c", "vol", "mass", "force", "weos", "rho_eos", "z_eos", "whg",
               "rho_hg", "z_hg"):
         setattr(s, f, FAKE)
     s.clock = FAKE
@@ -188,7 +188,7 @@ def test_invalid_hydro_arguments_are_rejected():
                 dict(perfo_param=2, perfo_items_per_lane=0), dict(perfo_param=2, perfo_items_per_lane=65)):
         expect(E, hstep, P, hydro_tech(**bad), 0, S)
     expect(E, hstep, P, hydro_tech(eos_history=2, eos_prediction=2), 0, hydro_state(weos=0))
-    expect(E, hstep, P, hydro_tech(hg_history=2, hg_prediction=2), 0, hydro_state(fhg=0))
+    expect(E, hstep, P, hydro_tech(hg_history=2, hg_prediction=2), 0, hydro_state(whg=0))
     expect(E, hstep, P, hydro_tech(hg_history=2, hg_prediction=2), 0, hydro_state(z_hg=0))
 
 

@@ -60,8 +60,6 @@ def to_oracle(h):
     s = oracle.HydroState(h.n, eos_h=t.eos[0] if t.eos else 0, hg_h=t.hg[0] if t.hg else 0)
     for f in ("x", "u", "mnode", "e", "p", "q", "c", "vol", "mass", "clock"):
         getattr(s, f)[...] = g[f]
-    if g["fhg"] is not None:
-        s.fhg[...] = g["fhg"]
     if t.eos:
         s.weos[...] = g["weos"]
         s.rho_eos[...] = g["rho_eos"]
@@ -70,6 +68,12 @@ def to_oracle(h):
         s.whg[...] = g["whg"]
         s.rho_hg[...] = g["rho_hg"]
         s.z_hg[...] = g["z_hg"]
+        # the GPU keeps the last accurate forces only as the newest window
+        # slot of each decision group; the oracle keeps them apart
+        hs, E = t.hg[0], h.n ** 3
+        pushes = g["z_hg"][np.arange(E) // _group(t.hg)]
+        newest = g["whg"].reshape(hs, 24, E)[(pushes - 1) % hs, :, np.arange(E)].T
+        s.fhg[...] = np.where(pushes > 0, newest, 0.0)
     return s
 
 
