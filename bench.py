@@ -465,11 +465,9 @@ def binomial_leg(torch, hpac, n=65536, steps=512):
 
 
 HYDRO_TECHS = {
-    # name: hydro technique arguments
+    # name: hydro technique arguments (the TAF grid is in HYDRO_SWEEP)
     "exact": {},
     "eos_taf_thread_h4_p2_0.001": dict(eos=(4, 2, 0.001, "thread")),
-    "eos_taf_wave_h2_p2_0.001": dict(eos=(2, 2, 0.001)),
-    "hg_taf_wave_h4_p4_0.05": dict(hg=(4, 4, 0.05)),
     "hg_perfo_small_M2_ipt2": dict(perfo=("small", 2, 2)),
     "hg_perfo_fini_20": dict(perfo=("fini", 20, 1)),
     "hg_perfo_ini_20": dict(perfo=("ini", 20, 1)),
