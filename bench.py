@@ -424,7 +424,7 @@ BO_TECHS = {
     # name: (entry point, options per unit, parameters)
     "exact": ("exact", 1, {}),
     "iact": ("iact", 16, dict(table_size=8, threshold=0.05)),
-    "taf": ("taf", 16, dict(history_size=4, prediction_size=4, rsd_threshold=0.01)),
+    "taf": ("taf", 8, dict(history_size=4, prediction_size=4, rsd_threshold=0.01)),
     "perfo": ("perfo", 10, dict(kind="small", param=10)),
 }
 
@@ -460,8 +460,30 @@ def binomial_leg(torch, hpac, n=65536, steps=512):
         for name in out:
             out[name]["speedup_vs_exact"] = out["exact"]["ms"] / out[name]["ms"]
         res[vname] = out
+    # options per unit: more options give the memo more reuse but fewer
+    # wavefronts (65,536 / IPT) to fill 1,024 SIMDs; each IPT on inputs in
+    # which every unit sees one tuple
+    study = {}
+    for ipt in (4, 8, 16, 32):
+        x = inputs.periodic(n, hpac.hpac_bo_units(n, ipt), jitter=1e-3)
+        xd = [torch.from_numpy(c).to(dev) for c in x]
+        ex = [torch.zeros(n, dtype=torch.float32, device=dev) for _ in range(2)]
+        e_ms = time_pairs(torch, {"t": [lambda: hpac.hpac_bo_exact(xd, ex, steps, items_per_lane=1)]}, 3, 1)["t"]
+        row = {"exact_ms": e_ms}
+        for name in ("iact", "taf"):
+            fn, _, params = BO_TECHS[name]
+            f = {"iact": hpac.hpac_bo_iact, "taf": hpac.hpac_bo_taf}[fn]
+            o = [torch.zeros(n, dtype=torch.float32, device=dev) for _ in range(2)]
+            ms = time_pairs(torch, {"t": [lambda f=f, o=o: f(xd, o, steps, items_per_lane=ipt, **params)]}, 3, 1)["t"]
+            cnt = torch.zeros(hpac.NUM_COUNTERS, dtype=torch.int64, device=dev)
+            f(xd, o, steps, items_per_lane=ipt, counters=cnt, **params)
+            torch.cuda.synchronize()
+            c = cnt.cpu().tolist()
+            row[name] = {"ms": ms, "speedup_vs_exact": e_ms / ms, "approx_frac": c[1] / max(c[0], 1),
+                         "mape_vs_exact": mape_torch(torch, ex, o)}
+        study[str(ipt)] = row
     return {"workload": "American call+put, %d-step CRR tree, %d options, one wavefront per option" % (steps, n),
-            "variants": res}
+            "variants": res, "unit_periodic_items_per_unit": study}
 
 
 HYDRO_TECHS = {

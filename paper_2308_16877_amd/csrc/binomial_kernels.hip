@@ -158,14 +158,41 @@ __device__ __forceinline__ uint32_t bo_trace_word(bool approx, bool voted, bool 
 
 }  // namespace
 
-// TECH: 0 exact, 1 iACT, 2 TAF, 3 perforation.  H: TAF history (1..8).
+// TECH: 0 exact, 1 iACT, 2 TAF, 3 perforation, 4 dense small/large
+// perforation.  H: TAF history (1..8).
+//
+// Dense perforation (no trace or counters): the region keeps no state, so
+// the options a herded small/large pattern keeps -- whole steps k, i.e. the
+// option ranges [kL, (k+1)L) -- can be priced by any wavefronts: one option
+// per wavefront over the kept ranges only, so every SIMD gets the same share
+// of trees whatever the options per unit.  The outputs are those of TECH 3.
 template <int C, int TECH, int H>
 __global__ void __launch_bounds__(256) k_binomial(BoArgs a) {
   __shared__ unsigned long long sums[4];
-  BoStats stats{a.counters, sums};
-  stats.begin();
   const int lane = lane_id();
   const int64_t unit = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (TECH == 4) {
+    // wavefront -> r-th kept step; kept steps repeat with period M: small
+    // keeps every position of a period but `special`, large only `special`
+    const int64_t r = unit / a.L;
+    const int64_t P = r / a.kept_per_period;
+    const int rem = (int)(r - P * a.kept_per_period);
+    const int pos = a.kind == 1 ? a.special : (rem < a.special ? rem : rem + 1);
+    const int64_t i = (P * a.param + pos) * a.L + (unit - r * a.L);
+    if (i < a.n) {
+      float x[5];
+#pragma unroll
+      for (int j = 0; j < 5; ++j) x[j] = a.in[j][i];
+      const BoOut y = bo_tree<C>(x[0], x[1], x[2], x[3], x[4], a.steps, a.american);
+      if (lane == 0) {
+        a.out[0][i] = y.call;
+        a.out[1][i] = y.put;
+      }
+    }
+    return;
+  }
+  BoStats stats{a.counters, sums};
+  stats.begin();
   unsigned long long visited = 0, approxd = 0;
   // iACT: lane e holds entry e
   float ex[5] = {0, 0, 0, 0, 0}, ey[2] = {0, 0};
@@ -281,6 +308,38 @@ int bo_nodes_per_lane(int steps) {
 
 template <int C, int TECH>
 static void bo_go_h(const BoArgs &a, int block, hipStream_t s) {
+  if (TECH == 3 && !a.trace && !a.counters && a.param > 0) {
+    if (a.kind == 0 || a.kind == 1) {
+      // small / large: the kept steps below the last one that holds options
+      const int M = a.param;
+      const int off = (int)(a.offset % M);
+      BoArgs b = a;
+      b.special = a.kind == 0 ? ((M - 1 - off) % M + M) % M : ((M - off) % M + M) % M;
+      b.kept_per_period = a.kind == 0 ? M - 1 : 1;
+      if (b.kept_per_period == 0) return;  // small with M = 1 drops every step
+      const int64_t steps = (a.n + a.L - 1) / a.L;
+      int64_t kept = (steps / M) * b.kept_per_period;
+      for (int64_t st = (steps / M) * M; st < steps; ++st) {
+        const int pos = (int)(st % M);
+        kept += a.kind == 0 ? pos != b.special : pos == b.special;
+      }
+      if (kept == 0) return;
+      hipLaunchKernelGGL((k_binomial<C, 4, 1>), dim3((unsigned)(kept * a.L * 64 / block)), dim3(block), 0, s, b);
+      return;
+    }
+    // ini / fini: the kept options are one contiguous range, one per unit
+    const int64_t cut = ((int64_t)a.param * a.n) / 100;
+    const int64_t lo = a.kind == 2 ? cut : 0;
+    BoArgs b = a;
+    b.n = a.n - cut;
+    if (b.n == 0) return;
+    b.ipt = 1;
+    b.L = bo_units(b.n, 1);
+    for (int j = 0; j < 5; ++j) b.in[j] = a.in[j] + lo;
+    for (int o = 0; o < 2; ++o) b.out[o] = a.out[o] + lo;
+    hipLaunchKernelGGL((k_binomial<C, 0, 1>), dim3((unsigned)(b.L * 64 / block)), dim3(block), 0, s, b);
+    return;
+  }
   const dim3 grid((unsigned)(a.L * 64 / block));
   if (TECH != 2) {
     hipLaunchKernelGGL((k_binomial<C, TECH, 1>), grid, dim3(block), 0, s, a);

@@ -18,6 +18,7 @@ struct BoArgs {
   float threshold;     // iACT distance / TAF RSD threshold
   int32_t hsize, psize;  // TAF
   int32_t kind, param, offset;  // perforation
+  int32_t kept_per_period, special;  // dense small/large perforation (set by the launcher)
   uint32_t *trace;     // optional, L * ipt words
   unsigned long long *counters;  // optional, 4
 };

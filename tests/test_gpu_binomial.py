@@ -157,6 +157,21 @@ def test_perforation_matches_oracle(kind, param, ipt):
     assert cnt[1] == skipped.sum()
 
 
+@pytest.mark.parametrize("kind,param,ipt,offset", [
+    ("small", 4, 8, 1), ("small", 10, 10, 0), ("small", 1, 4, 0), ("large", 3, 6, 2), ("ini", 30, 2, 0),
+    ("fini", 25, 3, 0), ("fini", 100, 2, 0),
+])
+def test_dense_perforation_matches_traced(kind, param, ipt, offset):
+    """Without trace or counters, small/large perforation prices only the
+    kept steps' options, one per wavefront, and ini/fini the kept range:
+    the same outputs, bit for bit, as the per-unit kernel."""
+    x = inputs.portfolio(3001, 256)
+    yt, _, _ = run(hpac.hpac_bo_perfo, x, 96, ipt, kind=kind, param=param, offset=offset)
+    yd, _, _ = run(hpac.hpac_bo_perfo, x, 96, ipt, trace=False, counters=False, kind=kind, param=param,
+                   offset=offset)
+    assert np.array_equal(yd, yt)
+
+
 def test_thresholds_zero_collapse_to_exact():
     x = inputs.periodic(4096, 8, jitter=1e-4)
     ye, _, _ = run(hpac.hpac_bo_exact, x, 64, 8)
