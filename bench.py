@@ -60,6 +60,8 @@ def parse():
 
 
 COPY_PROBE_BYTES = 256 << 20
+# the structured-locality variants: (name, pool period)
+STRUCTURED = (("lane_periodic_1024", 1024), ("wave_periodic_2", 2))
 
 
 def pmc_probe(torch, hpac, x_copies, n):
@@ -71,6 +73,15 @@ def pmc_probe(torch, hpac, x_copies, n):
     for r in range(3):
         for t in TECHS:
             launch(hpac, t, x_copies[r % len(x_copies)], outs)
+    # the same launches on the two structured-locality variants, in turn
+    # (dispatches 3..5 and 6..8 of each technique kernel)
+    from paper_2308_16877_amd import inputs
+    for _, period in STRUCTURED:
+        xs = [torch.from_numpy(c).to(dev) for c in inputs.periodic(n, period, jitter=1e-3)]
+        for r in range(3):
+            for t in TECHS:
+                launch(hpac, t, xs, outs)
+        del xs
     src = torch.zeros(COPY_PROBE_BYTES // 4, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
     for r in range(3):
@@ -87,7 +98,6 @@ def pmc_probe(torch, hpac, x_copies, n):
     h.run(3)
     del h
     # the Binomial Options techniques on the structured variant of their leg
-    from paper_2308_16877_amd import inputs
     n_bo = 65536
     xb = [torch.from_numpy(c).to(dev) for c in inputs.periodic(n_bo, hpac.hpac_bo_units(n_bo, 16), jitter=1e-3)]
     ob = [torch.zeros(n_bo, dtype=torch.float32, device=dev) for _ in range(2)]
@@ -123,6 +133,30 @@ def committed_profile(kind, kernel, workload):
     if d.get("kernel_source_sha") != kernel_source_sha(kernel):
         return None
     return d
+
+
+def skipped_work_counters():
+    """Work each technique kernel skips, from the committed counter summaries
+    of the counter probe (rocprofv3 --pmc on the same 2^24 options): per
+    workload, 1 - issued VALU / the exact kernel's and 1 - HBM bytes / the
+    exact kernel's, per launch.  None where a summary is missing or stale."""
+    out = {}
+    for workload in ["bs2p24_sorted"] + ["bs2p24_" + v for v, _ in STRUCTURED]:
+        base_v = committed_profile("valu", KERNEL_NAMES["exact"], workload)
+        base_t = committed_profile("traffic", KERNEL_NAMES["exact"], workload)
+        row = {}
+        for t, kernel in KERNEL_NAMES.items():
+            if t == "exact":
+                continue
+            v = committed_profile("valu", kernel, workload)
+            tr = committed_profile("traffic", kernel, workload)
+            row[t] = {
+                "valu_skipped_frac": (1 - v["lane_instructions_per_dispatch"] / base_v["lane_instructions_per_dispatch"])
+                if v and base_v else None,
+                "hbm_bytes_saved_frac": (1 - tr["hbm_bytes_per_launch"] / base_t["hbm_bytes_per_launch"])
+                if tr and base_t else None}
+        out[workload] = row
+    return out
 
 
 def measured_traffic(kernel, workload, launches_bytes):
@@ -768,6 +802,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parameter_sweep": sweep,
+        "skipped_work_counters": skipped_work_counters(),
         "structured_locality": structured,
         "greeks": greeks,
         "precision": precision,

@@ -3,9 +3,12 @@ profiles/.
 
   python -m paper_2308_16877_amd.profiling trace <kernel_stats.csv> <kernel_trace.csv> <bench.json> <out.txt> "<command>"
   python -m paper_2308_16877_amd.profiling traffic <fetch counter_collection.csv> <write counter_collection.csv> \
-        <kernel-name-substring> <workload> <out.json> "<fetch command>" "<write command>"
+        <kernel-name-substring> <workload> <out.json> "<fetch command>" "<write command>" [a:b]
   python -m paper_2308_16877_amd.profiling valu <sq counter_collection.csv> <kernel-name-substring> <workload> \
-        <items per dispatch> <out.json> "<command>"
+        <items per dispatch> <out.json> "<command>" [a:b]
+
+The optional a:b keeps dispatches a..b-1 of the kernel, in dispatch order
+(the counter probe launches each workload's kernels three times in turn).
   python -m paper_2308_16877_amd.profiling kernels <kernel_stats.csv> <name-substring> <out.txt> "<title>" "<command>"
 
 The traffic summary scales each kernel's FETCH_SIZE and WRITE_SIZE (KiB per
@@ -105,12 +108,23 @@ def _pmc(path, counter):
     return rows
 
 
-def traffic_summary(fetch_csv, write_csv, kernel_sub, workload, out_json, fetch_cmd, write_cmd):
+def _dispatch_slice(rows, dispatches):
+    """The rows of dispatches a..b-1 (in dispatch order) for "a:b", else all."""
+    if not dispatches:
+        return rows
+    a, b = (int(v) for v in dispatches.split(":"))
+    ids = sorted({int(r["Dispatch_Id"]) for r in rows})[a:b]
+    keep = set(ids)
+    return [r for r in rows if int(r["Dispatch_Id"]) in keep]
+
+
+def traffic_summary(fetch_csv, write_csv, kernel_sub, workload, out_json, fetch_cmd, write_cmd, dispatches=None):
     res = {}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rows = _pmc(path, counter)
         copy = [float(r["Counter_Value"]) for r in rows if _kernel_match(r["Kernel_Name"], COPY_KERNEL)]
-        kern = [float(r["Counter_Value"]) for r in rows if _kernel_match(r["Kernel_Name"], kernel_sub)]
+        kern = [float(r["Counter_Value"])
+                for r in _dispatch_slice([r for r in rows if _kernel_match(r["Kernel_Name"], kernel_sub)], dispatches)]
         if not copy or not kern:
             raise SystemExit("no %s rows for %s or the copy probe in %s" % (counter, kernel_sub, path))
         copy_kib = sum(copy) / len(copy)
@@ -122,7 +136,7 @@ def traffic_summary(fetch_csv, write_csv, kernel_sub, workload, out_json, fetch_
     out = {"kernel": kernel_sub, "workload": workload, "kernel_source_sha": kernel_source_sha(kernel_sub),
            "hbm_bytes_per_launch": res["FETCH_SIZE"]["bytes_per_dispatch"] + res["WRITE_SIZE"]["bytes_per_dispatch"],
            "fetch": res["FETCH_SIZE"], "write": res["WRITE_SIZE"],
-           "commands": [fetch_cmd, write_cmd],
+           "commands": [fetch_cmd, write_cmd], "dispatches": dispatches or "all",
            "copy_probe_bytes": COPY_BYTES}
     json.dump(out, open(out_json, "w"), indent=1)
     return out
@@ -137,11 +151,12 @@ def _kernel_match(name, sub):
     return base.startswith("hpac::" + sub + "<") or base == "hpac::" + sub
 
 
-def valu_summary(sq_csv, kernel_sub, workload, items, out_json, command):
+def valu_summary(sq_csv, kernel_sub, workload, items, out_json, command, dispatches=None):
     """Vector instructions issued per dispatch (SQ_INSTS_VALU, wave
     instructions, summed over the chip) and the other SQ counters of the same
     run, for the kernel whose name is hpac::<kernel_sub><...>."""
-    rows = [r for r in csv.DictReader(open(sq_csv)) if _kernel_match(r["Kernel_Name"], kernel_sub)]
+    rows = _dispatch_slice([r for r in csv.DictReader(open(sq_csv)) if _kernel_match(r["Kernel_Name"], kernel_sub)],
+                           dispatches)
     if not rows:
         raise SystemExit("no rows for %s in %s" % (kernel_sub, sq_csv))
     per = {}
@@ -153,7 +168,7 @@ def valu_summary(sq_csv, kernel_sub, workload, items, out_json, command):
            "dispatches": len(per.get("SQ_INSTS_VALU", [])), "counters_per_dispatch": avg,
            "lane_instructions_per_dispatch": avg["SQ_INSTS_VALU"] * 64.0,
            "items_per_dispatch": items, "valu_instructions_per_item": avg["SQ_INSTS_VALU"] * 64.0 / items,
-           "command": command}
+           "command": command, "dispatches": dispatches or "all"}
     json.dump(out, open(out_json, "w"), indent=1)
     return out
 
@@ -176,9 +191,9 @@ if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace_summary(*sys.argv[2:7])
     elif sys.argv[1] == "traffic":
-        print(json.dumps(traffic_summary(*sys.argv[2:9]), indent=1))
+        print(json.dumps(traffic_summary(*sys.argv[2:10]), indent=1))
     elif sys.argv[1] == "valu":
-        print(json.dumps(valu_summary(*sys.argv[2:8]), indent=1))
+        print(json.dumps(valu_summary(*sys.argv[2:9]), indent=1))
     elif sys.argv[1] == "kernels":
         kernels_summary(*sys.argv[2:7])
     else:
