@@ -121,8 +121,10 @@ struct LaneGeom {
   int64_t l;      // logical lane
   int64_t wbase;  // first lane of the wave
   int64_t bbase;  // first lane of the block
-  __device__ __forceinline__ LaneGeom() {
-    bbase = (int64_t)blockIdx.x * blockDim.x;
+  __device__ __forceinline__ LaneGeom() : LaneGeom((int64_t)blockIdx.x) {}
+  // the lanes of workgroup `block` of the full grid
+  __device__ __forceinline__ explicit LaneGeom(int64_t block) {
+    bbase = block * blockDim.x;
     l = bbase + threadIdx.x;
     wbase = l - lane_id();
   }
@@ -170,30 +172,44 @@ __device__ __forceinline__ void step_loop(int ipt, float (&xa)[N], float (&xb)[N
 
 // --------------------------------------------------------------- exact path
 
+// The counted variants (kStats, k_perfo) run a grid of at most
+// kCountedGrid workgroups that stride over the workgroups of the full grid:
+// each physical workgroup adds into the caller's counters once, since
+// same-address atomics from tens of thousands of workgroups serialize.
+constexpr unsigned kCountedGrid = 2048;
+
 template <class R, bool kStats>
 __global__ void __launch_bounds__(256) k_exact(KArgs a) {
   __shared__ unsigned long long sums[4];
-  const LaneGeom g;
   StatsSink sink{kStats ? a.counters : nullptr, sums};
   sink.begin();
   WaveStats st;
-  float xa[R::kIn], xb[R::kIn];
-  load_first<R>(a, g, true, xa);
-  step_loop(a.ipt, xa, xb, [&](int k, float (&x)[R::kIn], float (&xn)[R::kIn]) {
-    if (!g.wave_has(a, k)) return false;
-    const bool active = g.active(a, k);
-    prefetch<R>(a, g, k + 1, true, xn);
-    if (active) {
-      float y[R::kOut];
-      R::eval(x, y);
-      store_outputs<R>(a, g.item(a, k), y);
-    }
-    if (kStats) {
-      st.add(popc(ballot(active)), 0, false);
-      if (a.trace && lane_id() == 0) a.trace[g.trace_index(a, k)] = trace_word(0, 0, -1, false, false);
-    }
-    return true;
-  });
+  auto run_block = [&](int64_t b) {
+    const LaneGeom g(b);
+    float xa[R::kIn], xb[R::kIn];
+    load_first<R>(a, g, true, xa);
+    step_loop(a.ipt, xa, xb, [&](int k, float (&x)[R::kIn], float (&xn)[R::kIn]) {
+      if (!g.wave_has(a, k)) return false;
+      const bool active = g.active(a, k);
+      prefetch<R>(a, g, k + 1, true, xn);
+      if (active) {
+        float y[R::kOut];
+        R::eval(x, y);
+        store_outputs<R>(a, g.item(a, k), y);
+      }
+      if (kStats) {
+        st.add(popc(ballot(active)), 0, false);
+        if (a.trace && lane_id() == 0) a.trace[g.trace_index(a, k)] = trace_word(0, 0, -1, false, false);
+      }
+      return true;
+    });
+  };
+  if (kStats) {
+    const int64_t blocks = (a.L + blockDim.x - 1) / blockDim.x;
+    for (int64_t b = blockIdx.x; b < blocks; b += gridDim.x) run_block(b);
+  } else {
+    run_block(blockIdx.x);  // the uncounted grid is the full grid
+  }
   sink.end(st);
 }
 
@@ -220,33 +236,36 @@ struct PerfoRule {
 template <class R>
 __global__ void __launch_bounds__(256) k_perfo(KArgs a, int kind, int param, int offset) {
   __shared__ unsigned long long sums[4];
-  const LaneGeom g;
   StatsSink sink{a.counters, sums};
   sink.begin();
   const PerfoRule rule{kind, param, offset, (kind == kIni || kind == kFini) ? ((int64_t)param * a.n) / 100 : 0};
   WaveStats st;
-  float xa[R::kIn], xb[R::kIn];
-  load_first<R>(a, g, !rule.skipped(0, g.item(a, 0), a.n), xa);
-  step_loop(a.ipt, xa, xb, [&](int k, float (&x)[R::kIn], float (&xn)[R::kIn]) {
-    if (!g.wave_has(a, k)) return false;
-    const int64_t i = g.item(a, k);
-    const bool active = g.active(a, k);
-    const bool skip = rule.skipped(k, i, a.n);
-    // the next executed step's inputs; dropped steps load nothing
-    prefetch<R>(a, g, k + 1, !rule.skipped(k + 1, g.item(a, k + 1), a.n), xn);
-    if (active && !skip) {
-      float y[R::kOut];
-      R::eval(x, y);
-      store_outputs<R>(a, i, y);
-    }
-    if (a.trace || a.counters) {
-      const int nact = popc(ballot(active));
-      const int nskip = popc(ballot(active && skip));
-      st.add(nact, nskip, nskip > 0);
-      if (a.trace && lane_id() == 0) a.trace[g.trace_index(a, k)] = trace_word(0, nskip, -1, nskip > 0, false);
-    }
-    return true;
-  });
+  const int64_t blocks = (a.L + blockDim.x - 1) / blockDim.x;
+  for (int64_t b = blockIdx.x; b < blocks; b += gridDim.x) {
+    const LaneGeom g(b);
+    float xa[R::kIn], xb[R::kIn];
+    load_first<R>(a, g, !rule.skipped(0, g.item(a, 0), a.n), xa);
+    step_loop(a.ipt, xa, xb, [&](int k, float (&x)[R::kIn], float (&xn)[R::kIn]) {
+      if (!g.wave_has(a, k)) return false;
+      const int64_t i = g.item(a, k);
+      const bool active = g.active(a, k);
+      const bool skip = rule.skipped(k, i, a.n);
+      // the next executed step's inputs; dropped steps load nothing
+      prefetch<R>(a, g, k + 1, !rule.skipped(k + 1, g.item(a, k + 1), a.n), xn);
+      if (active && !skip) {
+        float y[R::kOut];
+        R::eval(x, y);
+        store_outputs<R>(a, i, y);
+      }
+      if (a.trace || a.counters) {
+        const int nact = popc(ballot(active));
+        const int nskip = popc(ballot(active && skip));
+        st.add(nact, nskip, nskip > 0);
+        if (a.trace && lane_id() == 0) a.trace[g.trace_index(a, k)] = trace_word(0, nskip, -1, nskip > 0, false);
+      }
+      return true;
+    });
+  }
   sink.end(st);
 }
 
@@ -597,6 +616,10 @@ __global__ void __launch_bounds__(256) k_copy(const float4 *__restrict__ src, fl
 // --------------------------------------------------------------- launchers
 
 static inline dim3 grid_for(const KArgs &a, int block) { return dim3((unsigned)((a.L + block - 1) / block)); }
+static inline dim3 counted_grid(const KArgs &a, int block) {
+  const dim3 g = grid_for(a, block);
+  return dim3(g.x < kCountedGrid ? g.x : kCountedGrid);
+}
 
 int64_t iact_lds_bytes(int region, int block, int table_size, int tables_per_wave) {
   const int E = region == 1 ? entry_floats<RegionBSPriceGrad>() : entry_floats<RegionBSPrice>();
@@ -638,7 +661,7 @@ struct ExactL {
   template <class R>
   hipError_t go() const {
     if (a.trace || a.counters)
-      hipLaunchKernelGGL((k_exact<R, true>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a);
+      hipLaunchKernelGGL((k_exact<R, true>), counted_grid(a, c.block), dim3(c.block), 0, c.stream, a);
     else
       hipLaunchKernelGGL((k_exact<R, false>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a);
     return hipGetLastError();
@@ -655,7 +678,7 @@ struct PerfoL {
   hipError_t go() const {
     // the dense paths launch up to ceil(n / block) workgroups
     if (a.trace || a.counters || param == 0 || (a.n + c.block - 1) / c.block + a.ipt > 2147483647) {
-      hipLaunchKernelGGL((k_perfo<R>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a, kind, param, offset);
+      hipLaunchKernelGGL((k_perfo<R>), counted_grid(a, c.block), dim3(c.block), 0, c.stream, a, kind, param, offset);
       return hipGetLastError();
     }
     if (kind == kIni || kind == kFini) {
