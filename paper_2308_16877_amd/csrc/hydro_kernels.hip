@@ -254,6 +254,15 @@ __device__ __forceinline__ bool window_rsd_below(const float *win, int64_t E, in
   return true;
 }
 
+// Workgroups are dispatched to the 8 XCDs in turn (workgroup b to XCD b mod
+// 8).  Renumbered this way, XCD x runs one contiguous stretch of the range,
+// so neighbouring planes of the mesh, which share nodes, meet in the same L2.
+// A bijection of [0, nb): XCD x takes nb/8 workgroups, one more if x < nb mod 8.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t x = b & 7, j = b >> 3, q = nb >> 3, r = nb & 7;
+  return x * q + (x < r ? x : r) + j;
+}
+
 __device__ __forceinline__ double block_min(double v, double *red) {
   red[threadIdx.x] = v;
   __syncthreads();
@@ -342,7 +351,7 @@ __global__ void __launch_bounds__(256) k_hydro_force(HydroArgs a) {
   __shared__ double red[256];
   const int n = a.n;
   const int64_t E = a.E;
-  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t l = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int lane = lane_id();
   constexpr bool kTaf = HG == kHgTafWave || HG == kHgTafThread;
   double bound = INFINITY;
@@ -465,7 +474,7 @@ __global__ void __launch_bounds__(256) k_hydro_dt(HydroArgs a, int64_t parts) {
 // ------------------------------------------------------------------ nodes
 
 __global__ void __launch_bounds__(256) k_hydro_node(HydroArgs a) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t v = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (v >= a.Nn) return;
   const int n = a.n;
   const int64_t m = n + 1, E = a.E;
@@ -499,7 +508,7 @@ __global__ void __launch_bounds__(256) k_hydro_eos(HydroArgs a) {
   constexpr bool kTaf = EOS != kEosExact;
   const int n = a.n;
   const int64_t E = a.E;
-  const int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t z = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int64_t w = z >> 6;
   if (w >= a.W) return;  // whole waves past the last element
   const int lane = lane_id();
