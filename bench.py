@@ -262,7 +262,17 @@ def time_pairs(torch, legs, steps, warmup):
 def greeks_leg(torch, hpac, x_dev, n, steps):
     """Call Greeks (upstream (1, 0)) for 2^24 options: exact forward + the
     recomputing adjoint, against iACT (table 16, threshold 0.05) on the
-    price-and-Jacobian region + the saved-Jacobian VJP."""
+    price-and-Jacobian region + the saved-Jacobian VJP; on the benchmark's
+    options and on the wave-periodic variant, where iACT finds reuse."""
+    from paper_2308_16877_amd import inputs
+    res = greeks_point(torch, hpac, x_dev, n, steps)
+    xs = [torch.from_numpy(c).to(x_dev[0].device) for c in inputs.periodic(n, 2, jitter=1e-3)]
+    res["wave_periodic_2"] = greeks_point(torch, hpac, xs, n, steps)
+    res["wave_periodic_2"]["workload"] = "the same on item i = pool tuple i mod 2, 1e-3 jitter (structured-locality variant)"
+    return res
+
+
+def greeks_point(torch, hpac, x_dev, n, steps):
     dev = x_dev[0].device
     f32 = dict(dtype=torch.float32, device=dev)
     ones = torch.ones(n, **f32)
