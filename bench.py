@@ -461,6 +461,23 @@ def hierarchy_and_ipt_leg(torch, hpac, n):
         res[tech] = {"variant": vname, "params": params, "exact_ms": exact_ms, "levels_at_ipt16": levels,
                      "items_per_lane_at_wave_level": ipts}
         del copies
+    # tables per wave (the paper's tables per warp): lane l sees pool tuple
+    # l mod 64 at every step, so a wave meets 64 tuples -- more than one
+    # 8-entry table holds -- while each lane alone meets one
+    xs = inputs.periodic(n, 64, jitter=1e-3)
+    copies = [[torch.from_numpy(c).to(dev) for c in xs] for _ in range(3)]
+    ex = [torch.zeros(n, dtype=torch.float32, device=dev) for _ in range(2)]
+    hpac.hpac_exact(copies[0], ex, items_per_lane=1)
+    exact_ms = technique_point(torch, hpac, copies, n, "exact", 1, {}, ex)["ms"]
+    tables = {}
+    for tpw in (1, 2, 4, 8, 16, 32, 64):
+        r = technique_point(torch, hpac, copies, n, "iact", 16,
+                            dict(table_size=8, threshold=0.05, tables_per_wave=tpw, level="wave"), ex)
+        r["speedup_vs_exact"] = exact_ms / r["ms"]
+        tables[str(tpw)] = r
+    res["iact_tables_per_wave"] = {"variant": "lane_periodic_64", "params": dict(table_size=8, threshold=0.05),
+                                   "items_per_lane": 16, "exact_ms": exact_ms, "tables_per_wave": tables}
+    del copies
     return res
 
 

@@ -300,6 +300,16 @@ __global__ void __launch_bounds__(256) k_perfo_dense(KArgs a, int blocks_per_ste
 template <class R>
 constexpr int entry_floats() { return (R::kIn + R::kOut + 3) & ~3; }
 
+// Floats from one table to the next: one more than a table's size when that
+// still fits the workgroup's 64 KiB of LDS.  With several tables per wave the
+// lanes read the same entry of different tables, and an odd stride puts
+// those words in different LDS banks.
+constexpr int64_t kIactLdsLimit = 65536;
+__host__ __device__ inline int iact_table_stride(int entry, int block, int tsize, int tpw) {
+  const int padded = tsize * entry + 1;
+  return (int64_t)(block / kWave) * tpw * padded * 4 <= kIactLdsLimit ? padded : tsize * entry;
+}
+
 // Squared Euclidean distance in FP32 with a fixed rounding sequence:
 // t0*t0, then fma(tj, tj, acc).  No other contraction is allowed here.
 template <int N>
@@ -327,7 +337,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
   const int wib = threadIdx.x >> 6;
   const int lpt = kWave / tpw;  // lanes per table
   const int tab_in_wave = lane / lpt;
-  float *tab = lds + ((size_t)wib * tpw + tab_in_wave) * tsize * E;
+  float *tab = lds + ((size_t)wib * tpw + tab_in_wave) * iact_table_stride(E, blockDim.x, tsize, tpw);
   StatsSink sink{a.counters, sums};
   sink.begin();
   BlockTally tally{tally_mem};
@@ -623,7 +633,8 @@ static inline dim3 counted_grid(const KArgs &a, int block) {
 
 int64_t iact_lds_bytes(int region, int block, int table_size, int tables_per_wave) {
   const int E = region == 1 ? entry_floats<RegionBSPriceGrad>() : entry_floats<RegionBSPrice>();
-  return (int64_t)(block / kWave) * tables_per_wave * table_size * E * (int64_t)sizeof(float);
+  return (int64_t)(block / kWave) * tables_per_wave * iact_table_stride(E, block, table_size, tables_per_wave) *
+         (int64_t)sizeof(float);
 }
 
 // (region, column type) -> region type.  Regions: 0 price, 1 price and
