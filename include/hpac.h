@@ -335,6 +335,14 @@ hpac_status hpac_hydro_init(const hpac_hydro_params *params, double e_origin, co
 hpac_status hpac_hydro_step(const hpac_hydro_params *params, const hpac_hydro_tech *tech, int32_t step,
                             const hpac_hydro_state *state, int8_t *dec_eos, int8_t *dec_hg, void *stream);
 
+/* `steps` (>= 0) timesteps with indices first_step, first_step + 1, ...:
+ * the same launches as that many hpac_hydro_step calls with u and unew
+ * swapped between them, issued from one host loop (no decision records).
+ * On return, in stream order, the latest velocities are in state->unew if
+ * `steps` is odd and in state->u if it is even. */
+hpac_status hpac_hydro_run(const hpac_hydro_params *params, const hpac_hydro_tech *tech, int32_t first_step,
+                           int32_t steps, const hpac_hydro_state *state, void *stream);
+
 /* ------------------------------------------------------------------------
  * Binomial Options.  One wavefront prices one option on an N-step
  * Cox-Ross-Rubinstein tree (dt = T/N, u = exp(v sqrt(dt)), d = 1/u,

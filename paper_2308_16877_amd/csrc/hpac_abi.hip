@@ -535,9 +535,10 @@ hpac_status hpac_hydro_init(const hpac_hydro_params *params, double e_origin, co
   return hip_status(fn, hpac::launch_hydro_init(a, e_origin, params->dt0, (hipStream_t)stream));
 }
 
-hpac_status hpac_hydro_step(const hpac_hydro_params *params, const hpac_hydro_tech *tech, int32_t step,
-                            const hpac_hydro_state *state, int8_t *dec_eos, int8_t *dec_hg, void *stream) {
-  const char *fn = "hpac_hydro_step";
+// Checks of a hydro step's arguments and its kernel arguments and modes.
+static hpac_status hydro_prepare(const char *fn, const hpac_hydro_params *params, const hpac_hydro_tech *tech,
+                                 int32_t step, const hpac_hydro_state *state, int8_t *dec_eos, int8_t *dec_hg,
+                                 hpac::HydroArgs *out, int *hg_mode, int *eos_mode_out) {
   hpac_status st = check_hydro_params(fn, params);
   if (st == HPAC_OK) st = check_hydro_state(fn, state);
   if (st != HPAC_OK) return st;
@@ -587,7 +588,42 @@ hpac_status hpac_hydro_step(const hpac_hydro_params *params, const hpac_hydro_te
   }
   int eos_mode = hpac::kEosExact;
   if (T.eos_history) eos_mode = T.eos_level == HPAC_LEVEL_THREAD ? hpac::kEosTafThread : hpac::kEosTafWave;
+  *out = a;
+  *hg_mode = mode;
+  *eos_mode_out = eos_mode;
+  return HPAC_OK;
+}
+
+hpac_status hpac_hydro_step(const hpac_hydro_params *params, const hpac_hydro_tech *tech, int32_t step,
+                            const hpac_hydro_state *state, int8_t *dec_eos, int8_t *dec_hg, void *stream) {
+  const char *fn = "hpac_hydro_step";
+  hpac::HydroArgs a;
+  int mode = 0, eos_mode = 0;
+  const hpac_status st = hydro_prepare(fn, params, tech, step, state, dec_eos, dec_hg, &a, &mode, &eos_mode);
+  if (st != HPAC_OK) return st;
   return hip_status(fn, hpac::launch_hydro_step(a, mode, eos_mode, (hipStream_t)stream));
+}
+
+hpac_status hpac_hydro_run(const hpac_hydro_params *params, const hpac_hydro_tech *tech, int32_t first_step,
+                           int32_t steps, const hpac_hydro_state *state, void *stream) {
+  const char *fn = "hpac_hydro_run";
+  if (steps < 0) return fail(HPAC_EINVAL, "%s: steps = %d must be >= 0", fn, steps);
+  if ((int64_t)first_step + steps > INT32_MAX) return fail(HPAC_EINVAL, "%s: step indices overflow int32", fn);
+  hpac::HydroArgs a;
+  int mode = 0, eos_mode = 0;
+  const hpac_status st = hydro_prepare(fn, params, tech, first_step, state, nullptr, nullptr, &a, &mode, &eos_mode);
+  if (st != HPAC_OK) return st;
+  for (int32_t k = 0; k < steps; ++k) {
+    a.step = first_step + k;
+    const hipError_t e = hpac::launch_hydro_step(a, mode, eos_mode, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_status(fn, e);
+    for (int d = 0; d < 3; ++d) {  // the new velocities are the next step's old ones
+      float *t = a.u[d];
+      a.u[d] = a.un[d];
+      a.un[d] = t;
+    }
+  }
+  return HPAC_OK;
 }
 
 hpac_status hpac_probe_copy(const void *src, void *dst, int64_t bytes, void *stream) {

@@ -125,6 +125,8 @@ def lib():
     L.hpac_hydro_init.restype = i32
     L.hpac_hydro_step.argtypes = [HP, HT, i32, HS, vp, vp, vp]
     L.hpac_hydro_step.restype = i32
+    L.hpac_hydro_run.argtypes = [HP, HT, i32, i32, HS, vp]
+    L.hpac_hydro_run.restype = i32
     L.hpac_bo_units.argtypes = [i64, i32]
     L.hpac_bo_units.restype = i64
     L.hpac_bo_exact.argtypes = [IO, i32, i32]
@@ -392,6 +394,11 @@ def hpac_hydro_step(params, tech, step, state, dec_eos=None, dec_hg=None, stream
     _call("hpac_hydro_step", lib().hpac_hydro_step(ctypes.byref(params), ctypes.byref(tech), int(step),
                                                    ctypes.byref(state), _addr(dec_eos), _addr(dec_hg),
                                                    _torch_stream(stream)))
+
+
+def hpac_hydro_run(params, tech, first_step, steps, state, stream=None):
+    _call("hpac_hydro_run", lib().hpac_hydro_run(ctypes.byref(params), ctypes.byref(tech), int(first_step),
+                                                 int(steps), ctypes.byref(state), _torch_stream(stream)))
 
 
 # ------------------------------------------------------------ binomial

@@ -95,15 +95,21 @@ class Hydro:
         """One timestep (index = number of steps taken so far)."""
         hpac.hpac_hydro_step(self.params, self.tech.c, self.steps, self.state,
                              self.dec_eos if record else None, self.dec_hg if record else None, stream)
+        self._swap_velocities()
+        self.steps += 1
+
+    def _swap_velocities(self):
         self.u, self.unew = self.unew, self.u
         for d in range(3):  # element-wise: ctypes array fields are views of the struct
             self.state.u[d] = self.u[d].data_ptr()
             self.state.unew[d] = self.unew[d].data_ptr()
-        self.steps += 1
 
-    def run(self, steps):
-        for _ in range(steps):
-            self.step()
+    def run(self, steps, stream=None):
+        """`steps` timesteps issued by the library's own loop (no records)."""
+        hpac.hpac_hydro_run(self.params, self.tech.c, self.steps, steps, self.state, stream)
+        if steps % 2:
+            self._swap_velocities()
+        self.steps += steps
 
     def time(self):
         return float(self.clock[0])

@@ -190,6 +190,13 @@ def test_invalid_hydro_arguments_are_rejected():
     expect(E, hstep, P, hydro_tech(eos_history=2, eos_prediction=2), 0, hydro_state(weos=0))
     expect(E, hstep, P, hydro_tech(hg_history=2, hg_prediction=2), 0, hydro_state(whg=0))
     expect(E, hstep, P, hydro_tech(hg_history=2, hg_prediction=2), 0, hydro_state(z_hg=0))
+    # the multi-step entry point checks the same arguments, and its own
+    hrun = lambda *a: hpac.hpac_hydro_run(*a, stream=0)
+    expect(E, hrun, P, T, 0, -1, S)
+    expect(E, hrun, P, T, 2 ** 31 - 10, 11, S)
+    expect(E, hrun, P, T, -1, 1, S)
+    expect(E, hrun, hydro_params(n=0), T, 0, 1, S)
+    expect(E, hrun, P, hydro_tech(hg_history=2, hg_prediction=2), 0, 1, hydro_state(whg=0))
 
 
 def bo_io(**kw):
