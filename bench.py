@@ -645,7 +645,7 @@ def hydro_sweep(torch, exact_ms_per_step, exact_q, ref64, n=90, steps=500):
     return {"points": pts, "best_at_qoi_err_0.005": {"technique": best, **ok[best]} if best else None}
 
 
-def hydro_cpu_baseline(steps=6, n=90):
+def hydro_cpu_baseline(steps=16, n=90):
     """The oracle hydro (FP64, exact regions) for a few steps of the same mesh."""
     import oracle
     s = oracle.hydro_init(n, (1.0 / 8.0) * n ** 3)
