@@ -389,6 +389,15 @@ int64_t hpac_trace_entries(int64_t n, int32_t items_per_lane);
  * calibrate hardware byte counters against a transfer of known size. */
 hpac_status hpac_probe_copy(const void *src, void *dst, int64_t bytes, void *stream);
 
+/* Measurement helper, not part of the method: `workgroups` (1..65536)
+ * workgroups of 256 lanes each issue `iters` (1..65536) x 64 independent
+ * FP32 fused multiply-adds, on 8 chains per lane; with scalar_operand != 0
+ * the multiplier and addend are wave-uniform kernel arguments (scalar
+ * register operands), else per-lane copies of them (vector registers).
+ * Each lane writes one float to out (workgroups * 256 floats, device), so
+ * the caller can time the launch: lane-FMAs = workgroups * 256 * iters * 64. */
+hpac_status hpac_probe_valu(float *out, int32_t workgroups, int32_t iters, int32_t scalar_operand, void *stream);
+
 /* Thread-local message describing the last non-OK status; never NULL. */
 const char *hpac_last_error(void);
 

@@ -623,6 +623,28 @@ __global__ void __launch_bounds__(256) k_copy(const float4 *__restrict__ src, fl
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) dst[i] = src[i];
 }
 
+// VALU issue rate: 8 independent FMA chains per lane.  With kScalar the
+// multiplier and addend stay wave-uniform (scalar-register operands); else
+// each lane holds its own copy (a + 0 * lane is not folded: it is -0 or NaN
+// for some a), so every operand is a vector register.
+template <bool kScalar>
+__global__ void __launch_bounds__(256) k_probe_valu(float *out, int iters, float a, float b) {
+  const float lanef = (float)threadIdx.x;
+  const float av = kScalar ? a : a + 0.0f * lanef, bv = kScalar ? b : b + 0.0f * lanef;
+  float r[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) r[j] = lanef * 1e-3f + (float)j;
+  for (int i = 0; i < iters; ++i)
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) r[j] = __builtin_fmaf(r[j], av, bv);
+  float s = 0.0f;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) s += r[j];
+  out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
 // --------------------------------------------------------------- launchers
 
 static inline dim3 grid_for(const KArgs &a, int block) { return dim3((unsigned)((a.L + block - 1) / block)); }
@@ -805,6 +827,14 @@ hipError_t launch_copy(const void *src, void *dst, int64_t bytes, hipStream_t st
   if (blocks > 8192) blocks = 8192;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, stream, (const float4 *)src, (float4 *)dst, n4);
+  return hipGetLastError();
+}
+
+hipError_t launch_probe_valu(float *out, int workgroups, int iters, bool scalar_operand, hipStream_t stream) {
+  if (scalar_operand)
+    hipLaunchKernelGGL(k_probe_valu<true>, dim3(workgroups), dim3(256), 0, stream, out, iters, 0.999f, 1e-3f);
+  else
+    hipLaunchKernelGGL(k_probe_valu<false>, dim3(workgroups), dim3(256), 0, stream, out, iters, 0.999f, 1e-3f);
   return hipGetLastError();
 }
 

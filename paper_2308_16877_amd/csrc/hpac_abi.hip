@@ -635,4 +635,12 @@ hpac_status hpac_probe_copy(const void *src, void *dst, int64_t bytes, void *str
   return hip_status(fn, hpac::launch_copy(src, dst, bytes, (hipStream_t)stream));
 }
 
+hpac_status hpac_probe_valu(float *out, int32_t workgroups, int32_t iters, int32_t scalar_operand, void *stream) {
+  const char *fn = "hpac_probe_valu";
+  if (workgroups < 1 || workgroups > 65536 || iters < 1 || iters > 65536)
+    return fail(HPAC_EINVAL, "%s: workgroups and iters must be in [1, 65536]", fn);
+  if (!out || (uintptr_t)out % 4) return fail(HPAC_EINVAL, "%s: out must be a 4-byte aligned device buffer", fn);
+  return hip_status(fn, hpac::launch_probe_valu(out, workgroups, iters, scalar_operand != 0, (hipStream_t)stream));
+}
+
 }  // extern "C"

@@ -35,6 +35,7 @@ hipError_t launch_taf(const LaunchCfg &c, const KArgs &a, int level, int history
                       float threshold);
 hipError_t launch_perfo(const LaunchCfg &c, const KArgs &a, int kind, int param, int offset);
 hipError_t launch_copy(const void *src, void *dst, int64_t bytes, hipStream_t stream);
+hipError_t launch_probe_valu(float *out, int workgroups, int iters, bool scalar_operand, hipStream_t stream);
 
 // Bytes of LDS one iACT workgroup needs.
 int64_t iact_lds_bytes(int region, int block, int table_size, int tables_per_wave);

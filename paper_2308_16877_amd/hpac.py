@@ -99,6 +99,8 @@ def lib():
     L.hpac_taf.argtypes = [IO, i32, i32, f32, i32]
     L.hpac_perfo.argtypes = [IO, i32, i32, i32]
     L.hpac_probe_copy.argtypes = [vp, vp, i64, vp]
+    L.hpac_probe_valu.argtypes = [vp, i32, i32, i32, vp]
+    L.hpac_probe_valu.restype = i32
     PP = ctypes.POINTER(ctypes.c_void_p)
     NP = ctypes.POINTER(hpac_mlp_norm)
     FP = ctypes.POINTER(ctypes.c_float)
@@ -337,6 +339,11 @@ def hpac_mlp_adam(grad_partials, blocks, params, m, v, lr, beta1, beta2, eps, st
 
 def hpac_probe_copy(src, dst, nbytes, stream=None):
     _call("hpac_probe_copy", lib().hpac_probe_copy(_addr(src), _addr(dst), nbytes, _stream(stream, [src, dst])))
+
+
+def hpac_probe_valu(out, workgroups, iters, scalar_operand, stream=None):
+    _call("hpac_probe_valu", lib().hpac_probe_valu(_addr(out), int(workgroups), int(iters), int(bool(scalar_operand)),
+                                                   _stream(stream, [out])))
 
 
 def hpac_num_lanes(n, items_per_lane):

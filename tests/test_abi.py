@@ -91,6 +91,10 @@ def test_invalid_technique_parameters_are_rejected():
     expect(E, hpac.hpac_perfo, kind="ini", param=101, **io())
     expect(E, hpac.hpac_perfo, kind="small", param=2, offset=-1, **io())
     expect(E, hpac.hpac_probe_copy, FAKE, FAKE, 15)
+    for wg, it in ((0, 1), (65537, 1), (1, 0), (1, 65537)):
+        expect(E, hpac.hpac_probe_valu, FAKE, wg, it, 0, stream=0)
+    expect(E, hpac.hpac_probe_valu, 0, 1, 1, 0, stream=0)
+    expect(E, hpac.hpac_probe_valu, FAKE + 2, 1, 1, 0, stream=0)
 
 
 def test_unsupported_requests():
