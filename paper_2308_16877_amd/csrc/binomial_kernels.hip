@@ -27,6 +27,7 @@
 // Node prices S u^(2i-n) are carried by one multiplication per step and
 // recomputed from exp2 every 32 steps, which bounds their FP32 drift.
 #include "launch_binomial.hpp"
+#include <type_traits>
 #include "wave.hpp"
 
 namespace hpac {
@@ -76,32 +77,43 @@ __device__ __forceinline__ BoOut bo_tree(float S, float K, float T, float r, flo
     Vc[c] = i <= N ? fmaxf(X[c] - K, 0.0f) : 0.0f;
     Vp[c] = i <= N ? fmaxf(K - X[c], 0.0f) : 0.0f;
   }
-  for (int n = N - 1; n >= 0; --n) {
-    const float nc = from_next_lane(Vc[0]), np = from_next_lane(Vp[0]);
-    if ((n & 31) == 0) {
+  // the step loop, with the exercise test compiled in or out (a runtime
+  // flag would cost two lane selects per node and step)
+  auto steps = [&](auto american_tag) {
+    constexpr bool kAmerican = decltype(american_tag)::value;
+    for (int n = N - 1; n >= 0; --n) {
+      const float nc = from_next_lane(Vc[0]), np = from_next_lane(Vp[0]);
+      if (kAmerican) {
+        if ((n & 31) == 0) {
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            const int i = lane * C + c;
+            X[c] = i <= n ? S * __builtin_amdgcn_exp2f((float)(2 * i - n) * log2u) : 0.0f;
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < C; ++c) X[c] *= uf;
+        }
+      }
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        const int i = lane * C + c;
-        X[c] = i <= n ? S * __builtin_amdgcn_exp2f((float)(2 * i - n) * log2u) : 0.0f;
+        const float up_c = c + 1 < C ? Vc[c + 1] : nc;
+        const float up_p = c + 1 < C ? Vp[c + 1] : np;
+        float vc = __builtin_fmaf(pu, up_c, pd * Vc[c]);
+        float vp = __builtin_fmaf(pu, up_p, pd * Vp[c]);
+        if (kAmerican) {
+          vc = fmaxf(vc, X[c] - K);
+          vp = fmaxf(vp, K - X[c]);
+        }
+        Vc[c] = vc;
+        Vp[c] = vp;
       }
-    } else {
-#pragma unroll
-      for (int c = 0; c < C; ++c) X[c] *= uf;
     }
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      const float up_c = c + 1 < C ? Vc[c + 1] : nc;
-      const float up_p = c + 1 < C ? Vp[c + 1] : np;
-      float vc = __builtin_fmaf(pu, up_c, pd * Vc[c]);
-      float vp = __builtin_fmaf(pu, up_p, pd * Vp[c]);
-      if (american) {
-        vc = fmaxf(vc, X[c] - K);
-        vp = fmaxf(vp, K - X[c]);
-      }
-      Vc[c] = vc;
-      Vp[c] = vp;
-    }
-  }
+  };
+  if (american)
+    steps(std::true_type{});
+  else
+    steps(std::false_type{});
   // node 0 is lane 0's first node
   BoOut o;
   o.call = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(Vc[0])));
