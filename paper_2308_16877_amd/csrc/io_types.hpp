@@ -9,12 +9,9 @@ namespace hpac {
 
 __device__ __forceinline__ float bf16_bits_to_float(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-// Round to nearest, ties to even (NaN kept quiet).
-__device__ __forceinline__ uint16_t float_to_bf16_bits(float f) {
-  const uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-}
+// Round to nearest, ties to even (NaN kept quiet): gfx950's conversion
+// instruction (v_cvt_pk_bf16_f32).
+__device__ __forceinline__ uint16_t float_to_bf16_bits(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
 struct IoF32 {
   using elem = float;

@@ -58,7 +58,7 @@ struct RegionBSPriceF16 {
 // to the nearest BF16.
 struct Bf {
   float v;
-  __device__ __forceinline__ static Bf r(float f) { return Bf{bf16_bits_to_float(float_to_bf16_bits(f))}; }
+  __device__ __forceinline__ static Bf r(float f) { return Bf{(float)(__bf16)f}; }
 };
 __device__ __forceinline__ Bf operator+(Bf a, Bf b) { return Bf::r(a.v + b.v); }
 __device__ __forceinline__ Bf operator-(Bf a, Bf b) { return Bf::r(a.v - b.v); }
