@@ -210,6 +210,7 @@ def run_workload(torch, hpac, x_copies, n, steps, warmup, with_stats=True):
     per = {t: [ev[s][j].elapsed_time(ev[s][j + 1]) for s in range(steps)] for j, t in enumerate(names)}
     res = {"total_ms": total_ms, "wall_s": wall, "host_enqueue_s": host_s,
            "per_kernel_ms": {t: sum(v) / len(v) for t, v in per.items()},
+           "per_kernel_median_ms": {t: sorted(v)[len(v) // 2] for t, v in per.items()},
            "per_kernel_min_ms": {t: min(v) for t, v in per.items()}}
     if with_stats:
         # one untimed launch per technique with counters on the same inputs
@@ -246,7 +247,8 @@ def summarize(res, n):
     out = {}
     for t, ms in res["per_kernel_ms"].items():
         st = res["stats"][t]
-        out[t] = {"ms": round(ms, 5), "items_per_s": n / (ms * 1e-3), "speedup_vs_exact": ex / ms,
+        out[t] = {"ms": round(ms, 5), "ms_median": round(res["per_kernel_median_ms"][t], 5),
+                  "items_per_s": n / (ms * 1e-3), "speedup_vs_exact": ex / ms,
                   "mape": st["mape"], "approx_frac": st["approx_frac"],
                   "items_per_lane": TECHS[t][1], "params": TECHS[t][2]}
     return out
