@@ -328,19 +328,22 @@ def precision_leg(torch, hpac, x_dev, n, steps):
     ref = [torch.zeros(n, dtype=torch.float32, device=x_dev[0].device) for _ in range(2)]
     hpac.hpac_exact(x_dev, ref, items_per_lane=1)
     variants = {
-        "fp32_body_fp32_columns": (hpac.REGION_BS_PRICE, torch.float32),
-        "fp32_body_fp16_columns": (hpac.REGION_BS_PRICE, torch.float16),
-        "fp32_body_bf16_columns": (hpac.REGION_BS_PRICE, torch.bfloat16),
-        "fp16_body_fp16_columns": (hpac.REGION_BS_PRICE_F16, torch.float16),
-        "bf16_body_bf16_columns": (hpac.REGION_BS_PRICE_BF16, torch.bfloat16),
-        "fp16_body_fp32_columns": (hpac.REGION_BS_PRICE_F16, torch.float32),
+        # name: (region, column type, items per lane; 2 pairs the FP16 body's items in packed FP16)
+        "fp32_body_fp32_columns": (hpac.REGION_BS_PRICE, torch.float32, 1),
+        "fp32_body_fp16_columns": (hpac.REGION_BS_PRICE, torch.float16, 1),
+        "fp32_body_bf16_columns": (hpac.REGION_BS_PRICE, torch.bfloat16, 1),
+        "fp16_body_fp16_columns": (hpac.REGION_BS_PRICE_F16, torch.float16, 1),
+        "fp16_body_fp16_columns_packed": (hpac.REGION_BS_PRICE_F16, torch.float16, 2),
+        "bf16_body_bf16_columns": (hpac.REGION_BS_PRICE_BF16, torch.bfloat16, 1),
+        "fp16_body_fp32_columns": (hpac.REGION_BS_PRICE_F16, torch.float32, 1),
+        "fp16_body_fp32_columns_packed": (hpac.REGION_BS_PRICE_F16, torch.float32, 2),
     }
     legs, outs = {}, {}
-    for name, (region, dt) in variants.items():
+    for name, (region, dt, ipt) in variants.items():
         xs = [c.to(dt) for c in x_dev]
         o = [torch.zeros(n, dtype=dt, device=x_dev[0].device) for _ in range(2)]
         outs[name] = o
-        legs[name] = [hpac.prepare("exact", xs, o, items_per_lane=1, block_size=256, stream=stream, region=region)]
+        legs[name] = [hpac.prepare("exact", xs, o, items_per_lane=ipt, block_size=256, stream=stream, region=region)]
     t = time_pairs(torch, legs, steps, 2)
     res = {}
     for name in variants:

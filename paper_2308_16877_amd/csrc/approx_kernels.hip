@@ -26,6 +26,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace hpac {
 
 enum { kThread = 0, kWaveLvl = 1, kBlock = 2 };
@@ -211,6 +213,37 @@ __global__ void __launch_bounds__(256) k_exact(KArgs a) {
     run_block(blockIdx.x);  // the uncounted grid is the full grid
   }
   sink.end(st);
+}
+
+// Regions that evaluate a pair of items at once (packed arithmetic).
+template <class R, class = void>
+struct IsPaired : std::false_type {};
+template <class R>
+struct IsPaired<R, std::void_t<decltype(R::kPaired)>> : std::bool_constant<R::kPaired> {};
+
+// Exact path of a paired region, uncounted, items per lane >= 2: steps k and
+// k + 1 of a lane go through one packed evaluation.  Same lanes and items as
+// k_exact; an odd last step is paired with a copy of itself.
+template <class R>
+__global__ void __launch_bounds__(256) k_exact_pairs(KArgs a) {
+  const LaneGeom g;
+  for (int k = 0; k < a.ipt; k += 2) {
+    if (!g.wave_has(a, k)) return;
+    const bool act0 = g.active(a, k);
+    const bool act1 = k + 1 < a.ipt && g.active(a, k + 1);
+    float x0[R::kIn], x1[R::kIn];
+    if (act0) load_inputs<R>(a, g.item(a, k), x0);
+    if (act1) load_inputs<R>(a, g.item(a, k + 1), x1);
+    if (act0) {
+      if (!act1)
+#pragma unroll
+        for (int j = 0; j < R::kIn; ++j) x1[j] = x0[j];
+      float y0[R::kOut], y1[R::kOut];
+      R::eval2(x0, x1, y0, y1);
+      store_outputs<R>(a, g.item(a, k), y0);
+      if (act1) store_outputs<R>(a, g.item(a, k + 1), y1);
+    }
+  }
 }
 
 // ---------------------------------------------------------------- perforation
@@ -695,8 +728,14 @@ struct ExactL {
   hipError_t go() const {
     if (a.trace || a.counters)
       hipLaunchKernelGGL((k_exact<R, true>), counted_grid(a, c.block), dim3(c.block), 0, c.stream, a);
-    else
+    else if constexpr (IsPaired<R>::value) {
+      if (a.ipt >= 2)
+        hipLaunchKernelGGL((k_exact_pairs<R>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a);
+      else
+        hipLaunchKernelGGL((k_exact<R, false>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a);
+    } else {
       hipLaunchKernelGGL((k_exact<R, false>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a);
+    }
     return hipGetLastError();
   }
 };

@@ -140,3 +140,21 @@ def test_prepared_launch_keeps_its_columns_alive():
     torch.cuda.synchronize()
     del junk
     assert all(torch.equal(a, b) for a, b in zip(first, out))
+
+
+@pytest.mark.parametrize("dtype", [hpac.F32, hpac.F16])
+def test_packed_fp16_pairs_equal_single_items(dtype):
+    """With two or more items per lane and no trace or counters, the FP16
+    body evaluates a lane's steps in pairs with packed FP16 arithmetic (an
+    odd last step paired with itself); every element is rounded as in the
+    single-item body, so the outputs are the same bit for bit (ragged n)."""
+    x = inputs.portfolio(50001, 1024)
+    xd = to_dev_typed(x, dtype)
+    ys = {}
+    for ipt in (1, 2, 3, 16):
+        out = [torch.zeros(x.shape[1], dtype=TYPES[dtype], device=DEV) for _ in range(2)]
+        hpac.hpac_exact(xd, out, items_per_lane=ipt, region=hpac.REGION_BS_PRICE_F16)
+        torch.cuda.synchronize()
+        ys[ipt] = np.stack([o.float().cpu().numpy() for o in out])
+    for ipt in (2, 3, 16):
+        assert np.array_equal(ys[ipt], ys[1]), ipt
