@@ -615,11 +615,12 @@ def hydro_leg(torch, n=90, steps=500):
 
 
 HYDRO_SWEEP = (
-    # TAF on each region at wave and thread level over the grid of the
+    # TAF on each region at thread, wave and block level over the grid of the
     # 2^24-option workload (prediction = window), and hourglass perforation
     # at 10, 20 and 50%
     [("%s_taf_%s_h%d_%g" % (region, level, h, th), {region: (h, h, th, level)})
-     for region in ("eos", "hg") for level in ("wave", "thread") for h in (2, 4, 8) for th in (0.001, 0.01, 0.1)]
+     for region in ("eos", "hg") for level in ("thread", "wave", "block") for h in (2, 4, 8)
+     for th in (0.001, 0.01, 0.1)]
     + [("hg_perfo_small_M%d" % m, dict(perfo=("small", m, 1))) for m in (10, 5, 2)])
 
 
@@ -646,7 +647,7 @@ def hydro_sweep(torch, exact_ms_per_step, exact_q, ref64, n=90, steps=500):
         if "eos" in kw or "hg" in kw:
             region = "eos" if "eos" in kw else "hg"
             h = Hydro(n, tech=Tech(**kw))
-            groups = h.W if kw[region][3] == "wave" else h.E
+            groups = {"thread": h.E, "wave": h.W, "block": -(-h.E // 256)}[kw[region][3]]
             acc = torch.zeros((), dtype=torch.int64, device="cuda:0")
             for _ in range(steps):
                 h.step(record=True)

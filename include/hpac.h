@@ -265,8 +265,9 @@ hpac_status hpac_mlp_adam(const float *grad_partials, int64_t blocks, float *par
  *    element loop at perfo_items_per_lane, offset = timestep (a skipped
  *    iteration adds nothing);
  *  - EOS region (e, p, q, c): TAF; approximated elements keep their values.
- * TAF decides per wave (majority of its 64 elements) or per element (thread
- * level), the two finest levels of section 3.1.2.
+ * TAF decides per element (thread level), per wave (majority of its 64
+ * elements) or per workgroup (block level: majority of 256 consecutive
+ * elements), the levels of section 3.1.2.
  * Layouts: element fields n^3 floats, element z = i + n (j + n k); node
  * fields (n+1)^3 floats, node i + (n+1) (j + (n+1) k); force is
  * [(corner * 3 + dim) * n^3 + z] with corner a + 2b + 4c for node
@@ -304,7 +305,7 @@ typedef struct hpac_hydro_state {
 typedef struct hpac_hydro_tech {
   int32_t eos_history, eos_prediction; /* EOS TAF; history 0 = exact */
   float eos_threshold;
-  int32_t eos_level;                   /* HPAC_LEVEL_WAVE or HPAC_LEVEL_THREAD */
+  int32_t eos_level;                   /* HPAC_LEVEL_THREAD, _WAVE or _BLOCK */
   int32_t hg_history, hg_prediction;   /* hourglass TAF; history 0 = none */
   float hg_threshold;
   int32_t hg_level;
@@ -313,8 +314,9 @@ typedef struct hpac_hydro_tech {
   int32_t perfo_items_per_lane;        /* 1..64 */
 } hpac_hydro_tech;
 
-/* Waves of the element loop, TAF decision groups at `level` (waves, or
- * elements at thread level: the size of rho_*, z_* and of dec_*), and
+/* Waves of the element loop, TAF decision groups at `level` (elements,
+ * waves or 256-element blocks: the size of dec_*; rho_* and z_* always have
+ * one entry per element), and
  * entries of dt_partials; -1 if an argument is invalid. */
 int64_t hpac_hydro_waves(int32_t n);
 int64_t hpac_hydro_groups(int32_t n, int32_t level);

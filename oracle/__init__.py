@@ -379,8 +379,8 @@ def hydro_init(n, e_origin, eos_h=0, hg_h=0, **par):
 
 def hydro_step(s, step, eos=None, hg=None, perfo=None, band=0.0, record=False):
     """One timestep in place.  eos / hg = (h, p, theta[, group]) for TAF on
-    the EOS / hourglass region, group = 64 (wave level, the default) or 1
-    (thread level); perfo = (kind, param, items_per_lane) for the hourglass
+    the EOS / hourglass region, group = 64 (wave level, the default), 1
+    (thread level) or 256 (block level, four waves); perfo = (kind, param, items_per_lane) for the hourglass
     region.  With record, returns per-group decisions and fragile flags
     {dec_eos, dec_hg, frag_eos, frag_hg}."""
     t = _HyTech(band=float(band), eos_group=GROUP_WAVE, hg_group=GROUP_WAVE)

@@ -70,6 +70,7 @@
 #include <string.h>
 
 #define HY_WAVE 64
+#define HY_BLOCK 256 /* a workgroup of four waves: the team level of section 3.1.2 */
 #define HY_MAX_H 16
 
 typedef struct {
@@ -102,7 +103,7 @@ typedef struct {
 typedef struct {
   int32_t eos_h, eos_p;  /* EOS TAF: history and prediction sizes (h = 0: exact) */
   double eos_theta;
-  int32_t eos_group;     /* lanes per decision: 1 (thread level) or 64 (wave level) */
+  int32_t eos_group;     /* lanes per decision: 1 (thread), 64 (wave) or 256 (block level) */
   int32_t hg_h, hg_p;    /* hourglass TAF (h = 0: none) */
   double hg_theta;
   int32_t hg_group;
@@ -374,7 +375,9 @@ int hy_step(const hy_par *P, const hy_tech *T, int32_t step, hy_state *S, hy_rec
   const int64_t n = P->n, m = n + 1, E = hy_elems(P), Nn = hy_nodes(P);
   if ((T->eos_h && (T->eos_h > HY_MAX_H || T->eos_p < 1)) || (T->hg_h && (T->hg_h > HY_MAX_H || T->hg_p < 1)))
     return -1;
-  if ((T->eos_group != 1 && T->eos_group != HY_WAVE) || (T->hg_group != 1 && T->hg_group != HY_WAVE)) return -1;
+  if ((T->eos_group != 1 && T->eos_group != HY_WAVE && T->eos_group != HY_BLOCK) ||
+      (T->hg_group != 1 && T->hg_group != HY_WAVE && T->hg_group != HY_BLOCK))
+    return -1;
   const int64_t GE = T->eos_group, GH = T->hg_group;
   const int64_t NGE = (E + GE - 1) / GE, NGH = (E + GH - 1) / GH;
   if (T->hg_h && T->perfo_param) return -1;

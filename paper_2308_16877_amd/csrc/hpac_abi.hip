@@ -510,6 +510,7 @@ int64_t hpac_hydro_groups(int32_t n, int32_t level) {
   if (n < 1 || n > 1000) return -1;
   if (level == HPAC_LEVEL_THREAD) return (int64_t)n * n * n;
   if (level == HPAC_LEVEL_WAVE) return hpac::hydro_lanes((int64_t)n * n * n, 1) / 64;
+  if (level == HPAC_LEVEL_BLOCK) return ((int64_t)n * n * n + hpac::kHydroBlock - 1) / hpac::kHydroBlock;
   return -1;
 }
 
@@ -549,9 +550,11 @@ static hpac_status hydro_prepare(const char *fn, const hpac_hydro_params *params
     return fail(HPAC_EINVAL, "%s: history sizes must be in [0, 8]", fn);
   if ((T.eos_history && T.eos_prediction < 1) || (T.hg_history && T.hg_prediction < 1))
     return fail(HPAC_EINVAL, "%s: prediction sizes must be >= 1", fn);
-  if ((T.eos_history && T.eos_level != HPAC_LEVEL_WAVE && T.eos_level != HPAC_LEVEL_THREAD) ||
-      (T.hg_history && T.hg_level != HPAC_LEVEL_WAVE && T.hg_level != HPAC_LEVEL_THREAD))
-    return fail(HPAC_EINVAL, "%s: hydro TAF levels are HPAC_LEVEL_WAVE or HPAC_LEVEL_THREAD", fn);
+  auto level_ok = [](int32_t lv) {
+    return lv == HPAC_LEVEL_WAVE || lv == HPAC_LEVEL_THREAD || lv == HPAC_LEVEL_BLOCK;
+  };
+  if ((T.eos_history && !level_ok(T.eos_level)) || (T.hg_history && !level_ok(T.hg_level)))
+    return fail(HPAC_EINVAL, "%s: hydro TAF levels are HPAC_LEVEL_THREAD, _WAVE or _BLOCK", fn);
   if (!(T.eos_threshold >= 0.0f) || !isfinite(T.eos_threshold) || !(T.hg_threshold >= 0.0f) ||
       !isfinite(T.hg_threshold))
     return fail(HPAC_EINVAL, "%s: thresholds must be finite and >= 0", fn);
@@ -580,14 +583,19 @@ static hpac_status hydro_prepare(const char *fn, const hpac_hydro_params *params
   a.perfo_param = T.perfo_param;
   int mode = hpac::kHgExact;
   if (T.hg_history) {
-    mode = T.hg_level == HPAC_LEVEL_THREAD ? hpac::kHgTafThread : hpac::kHgTafWave;
+    mode = T.hg_level == HPAC_LEVEL_THREAD ? hpac::kHgTafThread
+         : T.hg_level == HPAC_LEVEL_BLOCK  ? hpac::kHgTafBlock
+                                           : hpac::kHgTafWave;
   } else if (T.perfo_param) {
     mode = hpac::kHgPerfo;
     a.hg_ipt = T.perfo_items_per_lane;
     a.hg_L = hpac::hydro_lanes(a.E, a.hg_ipt);
   }
   int eos_mode = hpac::kEosExact;
-  if (T.eos_history) eos_mode = T.eos_level == HPAC_LEVEL_THREAD ? hpac::kEosTafThread : hpac::kEosTafWave;
+  if (T.eos_history)
+    eos_mode = T.eos_level == HPAC_LEVEL_THREAD ? hpac::kEosTafThread
+             : T.eos_level == HPAC_LEVEL_BLOCK  ? hpac::kEosTafBlock
+                                                : hpac::kEosTafWave;
   *out = a;
   *hg_mode = mode;
   *eos_mode_out = eos_mode;

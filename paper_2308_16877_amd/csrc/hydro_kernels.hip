@@ -351,9 +351,15 @@ __global__ void __launch_bounds__(256) k_hydro_force(HydroArgs a) {
   __shared__ double red[256];
   const int n = a.n;
   const int64_t E = a.E;
-  const int64_t l = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);  // element block: the block-level group
+  const int64_t l = blk * blockDim.x + threadIdx.x;
   const int lane = lane_id();
-  constexpr bool kTaf = HG == kHgTafWave || HG == kHgTafThread;
+  constexpr bool kTaf = HG == kHgTafWave || HG == kHgTafThread || HG == kHgTafBlock;
+  __shared__ int tally[3];  // block level: active elements, votes to approximate, waves that voted
+  if (HG == kHgTafBlock) {
+    if (threadIdx.x < 3) tally[threadIdx.x] = 0;
+    __syncthreads();
+  }
   double bound = INFINITY;
   for (int k = 0; k < a.hg_ipt; ++k) {
     const int64_t z = l + (int64_t)k * a.hg_L;
@@ -380,6 +386,11 @@ __global__ void __launch_bounds__(256) k_hydro_force(HydroArgs a) {
     if (HG == kHgTafThread && active) {
       rho = a.rho_hg[z];
       pushes = a.z_hg[z];
+      compute_hg = rho <= 0;
+    }
+    if (HG == kHgTafBlock) {
+      rho = a.rho_hg[blk];
+      pushes = a.z_hg[blk];
       compute_hg = rho <= 0;
     }
     bool crit = false, voted = false;
@@ -452,6 +463,26 @@ __global__ void __launch_bounds__(256) k_hydro_force(HydroArgs a) {
         if (a.dec_hg) a.dec_hg[w] = compute_hg ? 0 : 1;
       }
     }
+    if (HG == kHgTafBlock) {  // every lane of the workgroup reaches the barrier
+      const uint64_t amask = ballot(active);
+      const uint64_t vmask = ballot(crit);
+      const bool any_vote = ballot(voted) != 0;
+      if (lane == 0 && compute_hg) {
+        atomicAdd(&tally[0], popc(amask));
+        atomicAdd(&tally[1], popc(vmask));
+        if (any_vote) atomicAdd(&tally[2], 1);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0 && blk * blockDim.x < E) {
+        if (!compute_hg) {
+          a.rho_hg[blk] = rho - 1;
+        } else {
+          a.z_hg[blk] = pushes + 1;
+          if (tally[2] > 0 && majority(tally[1], tally[0])) a.rho_hg[blk] = a.hg_p;
+        }
+        if (a.dec_hg) a.dec_hg[blk] = compute_hg ? 0 : 1;
+      }
+    }
   }
   const double m = block_min(bound, red);
   if (threadIdx.x == 0) a.dt_partials[blockIdx.x] = m;
@@ -508,12 +539,29 @@ __global__ void __launch_bounds__(256) k_hydro_eos(HydroArgs a) {
   constexpr bool kTaf = EOS != kEosExact;
   const int n = a.n;
   const int64_t E = a.E;
-  const int64_t z = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);  // element block: the block-level group
+  const int64_t z = blk * blockDim.x + threadIdx.x;
   const int64_t w = z >> 6;
-  if (w >= a.W) return;  // whole waves past the last element
+  // whole waves past the last element leave, except at block level, where
+  // every lane of the workgroup must reach its barriers
+  if (EOS != kEosTafBlock && w >= a.W) return;
   const int lane = lane_id();
   const bool active = z < E;
   int pushes = 0;
+  __shared__ int tally[3];  // block level: active elements, votes to approximate, waves that voted
+  if (EOS == kEosTafBlock) {
+    const int rho = a.rho_eos[blk];
+    if (rho > 0) {  // the same for the whole workgroup
+      if (threadIdx.x == 0) {
+        a.rho_eos[blk] = rho - 1;
+        if (a.dec_eos) a.dec_eos[blk] = 1;
+      }
+      return;
+    }
+    pushes = a.z_eos[blk];
+    if (threadIdx.x < 3) tally[threadIdx.x] = 0;
+    __syncthreads();
+  }
   if (EOS == kEosTafWave) {
     const int rho = a.rho_eos[w];
     if (rho > 0) {
@@ -595,6 +643,22 @@ __global__ void __launch_bounds__(256) k_hydro_eos(HydroArgs a) {
       if (a.dec_eos) a.dec_eos[w] = 0;
     }
   }
+  if (EOS == kEosTafBlock) {
+    const uint64_t amask = ballot(active);
+    const uint64_t vmask = ballot(crit);
+    const bool any_vote = ballot(voted) != 0;
+    if (lane == 0) {
+      atomicAdd(&tally[0], popc(amask));
+      atomicAdd(&tally[1], popc(vmask));
+      if (any_vote) atomicAdd(&tally[2], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      a.z_eos[blk] = pushes + 1;
+      if (tally[2] > 0 && majority(tally[1], tally[0])) a.rho_eos[blk] = a.eos_p;
+      if (a.dec_eos) a.dec_eos[blk] = 0;
+    }
+  }
 }
 
 // --------------------------------------------------------------- launchers
@@ -622,6 +686,7 @@ hipError_t launch_hydro_step(const HydroArgs &a, int hg_mode, int eos_mode, hipS
     case kHgExact: hipLaunchKernelGGL(k_hydro_force<kHgExact>, dim3(fblocks), dim3(256), 0, s, a); break;
     case kHgTafWave: hipLaunchKernelGGL(k_hydro_force<kHgTafWave>, dim3(fblocks), dim3(256), 0, s, a); break;
     case kHgTafThread: hipLaunchKernelGGL(k_hydro_force<kHgTafThread>, dim3(fblocks), dim3(256), 0, s, a); break;
+    case kHgTafBlock: hipLaunchKernelGGL(k_hydro_force<kHgTafBlock>, dim3(fblocks), dim3(256), 0, s, a); break;
     case kHgNone: hipLaunchKernelGGL(k_hydro_force<kHgNone>, dim3(fblocks), dim3(256), 0, s, a); break;
     default: hipLaunchKernelGGL(k_hydro_force<kHgPerfo>, dim3(fblocks), dim3(256), 0, s, a); break;
   }
@@ -631,7 +696,8 @@ hipError_t launch_hydro_step(const HydroArgs &a, int hg_mode, int eos_mode, hipS
   switch (eos_mode) {
     case kEosExact: hipLaunchKernelGGL(k_hydro_eos<kEosExact>, dim3(eblocks), dim3(256), 0, s, a); break;
     case kEosTafWave: hipLaunchKernelGGL(k_hydro_eos<kEosTafWave>, dim3(eblocks), dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL(k_hydro_eos<kEosTafThread>, dim3(eblocks), dim3(256), 0, s, a); break;
+    case kEosTafThread: hipLaunchKernelGGL(k_hydro_eos<kEosTafThread>, dim3(eblocks), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL(k_hydro_eos<kEosTafBlock>, dim3(eblocks), dim3(256), 0, s, a); break;
   }
   return hipGetLastError();
 }

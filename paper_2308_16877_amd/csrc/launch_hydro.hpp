@@ -7,8 +7,9 @@ namespace hpac {
 
 // Lagrangian hydro (hydro_kernels.hip).  Region modes (kHgNone: no
 // hourglass force, a step that herded perforation drops as a whole):
-constexpr int kHgExact = 0, kHgTafWave = 1, kHgTafThread = 2, kHgPerfo = 3, kHgNone = 4;
-constexpr int kEosExact = 0, kEosTafWave = 1, kEosTafThread = 2;
+constexpr int kHgExact = 0, kHgTafWave = 1, kHgTafThread = 2, kHgPerfo = 3, kHgNone = 4, kHgTafBlock = 5;
+constexpr int kEosExact = 0, kEosTafWave = 1, kEosTafThread = 2, kEosTafBlock = 3;
+constexpr int kHydroBlock = 256;  // elements of a workgroup, the block-level decision group
 
 struct HydroArgs {
   int n;                  // elements per side

@@ -25,7 +25,7 @@ def sedov_origin_energy(n, side=1.0, energy=1.0):
 
 class Tech:
     """Technique of the hydro regions: eos / hg = (history, prediction,
-    threshold[, level]) for TAF, level "wave" (default) or "thread";
+    threshold[, level]) for TAF, level "wave" (default), "thread" or "block";
     perfo = (kind, param, items_per_lane) for the hourglass region."""
 
     def __init__(self, eos=None, hg=None, perfo=None):
@@ -63,7 +63,7 @@ class Hydro:
         self.force = torch.zeros(24, E, **f32)
         t = self.tech
         i32 = dict(dtype=torch.int32, device=device)
-        # decision-group state: one entry per element covers both levels
+        # decision-group state: one entry per element covers every level
         self.weos = torch.zeros(max(t.eos[0], 1) * 4, E, **f32) if t.eos else None
         self.rho_eos = torch.zeros(E, **i32) if t.eos else None
         self.z_eos = torch.zeros(E, **i32) if t.eos else None

@@ -157,7 +157,8 @@ def test_hydro_sizes():
     assert hpac.hpac_hydro_waves(90) == (90 ** 3 + 63) // 64
     assert hpac.hpac_hydro_groups(90, hpac.LEVEL_THREAD) == 90 ** 3
     assert hpac.hpac_hydro_groups(90, hpac.LEVEL_WAVE) == (90 ** 3 + 63) // 64
-    assert hpac.hpac_hydro_groups(90, hpac.LEVEL_BLOCK) == -1
+    assert hpac.hpac_hydro_groups(90, hpac.LEVEL_BLOCK) == (90 ** 3 + 255) // 256
+    assert hpac.hpac_hydro_groups(90, 3) == -1
     assert hpac.hpac_hydro_partials(90) == ((90 ** 3 + 63) // 64 * 64 + 255) // 256
     assert hpac.hpac_hydro_waves(0) == -1 and hpac.hpac_hydro_waves(1001) == -1
 
@@ -185,7 +186,7 @@ def test_invalid_hydro_arguments_are_rejected():
     expect(E, hstep, P, T, 0, hydro_state(clock=FAKE + 4))
     for bad in (dict(eos_history=9, eos_prediction=1), dict(eos_history=2, eos_prediction=0),
                 dict(hg_history=-1), dict(eos_history=2, eos_prediction=2, eos_threshold=-0.1),
-                dict(eos_history=2, eos_prediction=2, eos_level=hpac.LEVEL_BLOCK),
+                dict(eos_history=2, eos_prediction=2, eos_level=3),
                 dict(hg_history=2, hg_prediction=2, perfo_param=2, perfo_items_per_lane=2),
                 dict(perfo_kind=4, perfo_param=2, perfo_items_per_lane=2),
                 dict(perfo_kind=hpac.PERFO_INI, perfo_param=101, perfo_items_per_lane=1),

@@ -38,7 +38,9 @@ def _device():
 
 def _group(t):
     level = t[3] if len(t) > 3 else "wave"
-    return 1 if level in ("thread", hpac.LEVEL_THREAD) else 64
+    if level in ("thread", hpac.LEVEL_THREAD):
+        return 1
+    return 256 if level in ("block", hpac.LEVEL_BLOCK) else 64
 
 
 def oracle_tech(tech):
@@ -166,6 +168,8 @@ TAF_CASES = [
     ("both", Tech(eos=(2, 8, 0.05), hg=(3, 2, 0.1))),
     ("eos_thread", Tech(eos=(4, 4, 0.01, "thread"))),
     ("both_thread", Tech(eos=(3, 2, 0.02, "thread"), hg=(2, 3, 0.05, "thread"))),
+    ("both_block", Tech(eos=(3, 2, 0.02, "block"), hg=(2, 3, 0.05, "block"))),
+    ("mixed_levels", Tech(eos=(2, 2, 0.01, "block"), hg=(4, 2, 0.05, "thread"))),
 ]
 
 
@@ -229,8 +233,8 @@ def test_full_mesh_steps():
 @pytest.mark.parametrize("n,tech", [
     (1, Tech()), (2, Tech(eos=(2, 2, 0.05))), (5, Tech(eos=(2, 3, 0.05), hg=(2, 2, 0.1))),
     (5, Tech(eos=(2, 3, 0.05, "thread"), hg=(3, 1, 0.1, "thread"))), (7, Tech(perfo=("small", 3, 4))),
-    (9, Tech(perfo=("large", 2, 64))),
-], ids=["n1", "n2_eos", "n5_both_wave", "n5_both_thread", "n7_small", "n9_large_ipt64"])
+    (9, Tech(perfo=("large", 2, 64))), (7, Tech(eos=(2, 2, 0.05, "block"), hg=(2, 2, 0.1, "block"))),
+], ids=["n1", "n2_eos", "n5_both_wave", "n5_both_thread", "n7_small", "n9_large_ipt64", "n7_both_block"])
 def test_small_and_ragged_meshes(n, tech):
     """Meshes of one element, of fewer elements than a wave, and with a
     ragged last wave (125 = 64 + 61 elements), stepped and replayed."""

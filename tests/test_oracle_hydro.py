@@ -290,3 +290,27 @@ def test_thread_level_taf_decides_per_element():
     ref, _ = run(8, 40)
     s, _ = run(8, 40, eos=(4, 4, 0.0, 1), hg=(2, 3, 0.0, 1))
     assert same_state(s, ref)
+
+
+def test_block_level_taf_decides_per_256_elements():
+    """Block level (section 3.1.2's team): 256 consecutive elements share one
+    countdown and vote by majority, so a ragged last block is a group of its
+    own; with a threshold no finite RSD reaches every block follows the h,
+    then (p approximate + 1 accurate) pattern; threshold 0 is exact; and a
+    block decides for elements that, deciding alone, disagree."""
+    h, p = 3, 2
+    s, recs = run(9, 20, eos=(h, p, 1e300, 256), hg=(h, p, 1e300, 256))
+    for region in ("dec_eos", "dec_hg"):
+        dec = np.stack([r[region] for r in recs])  # (steps, blocks)
+        assert dec.shape[1] == -(-9 ** 3 // 256)
+        expect = [0] * h + ([1] * p + [0]) * 10
+        assert all(list(dec[:, b]) == expect[:20] for b in range(dec.shape[1]))
+    ref, _ = run(8, 40)
+    s, _ = run(8, 40, eos=(4, 4, 0.0, 256), hg=(2, 3, 0.0, 256))
+    assert same_state(s, ref)
+    _, rt = run(10, 60, eos=(4, 4, 0.01, 1))
+    split = 0  # blocks whose elements, deciding alone, disagree at some step
+    for r in rt:
+        t = r["dec_eos"][:(len(r["dec_eos"]) // 256) * 256].reshape(-1, 256)
+        split += int(np.sum((t == 1).any(axis=1) & (t == 0).any(axis=1)))
+    assert split > 0
