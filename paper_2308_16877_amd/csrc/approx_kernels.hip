@@ -333,32 +333,37 @@ __global__ void __launch_bounds__(256) k_perfo_dense(KArgs a, int blocks_per_ste
 template <class R>
 constexpr int entry_floats() { return (R::kIn + R::kOut + 3) & ~3; }
 
-// Floats from one table to the next: one more than a table's size when that
-// still fits the workgroup's 64 KiB of LDS.  With several tables per wave the
-// lanes read the same entry of different tables, and an odd stride puts
-// those words in different LDS banks.
+// LDS layout of a wave's tables.  With several tables per wave the lanes
+// read the same word of different tables at once: tables one float more
+// than their size apart (an odd stride) put those words in different banks,
+// when that still fits the workgroup's 64 KiB of LDS; otherwise the tables
+// are interleaved word by word (word j of entry e of table t at
+// (e * entry + j) * tables + t), which needs no pad and is read conflict-free
+// at the price of computed addresses.
 constexpr int64_t kIactLdsLimit = 65536;
+__host__ __device__ inline bool iact_interleaved(int entry, int block, int tsize, int tpw) {
+  return tpw > 1 && (int64_t)(block / kWave) * tpw * (tsize * entry + 1) * 4 > kIactLdsLimit;
+}
 __host__ __device__ inline int iact_table_stride(int entry, int block, int tsize, int tpw) {
-  const int padded = tsize * entry + 1;
-  return (int64_t)(block / kWave) * tpw * padded * 4 <= kIactLdsLimit ? padded : tsize * entry;
+  return iact_interleaved(entry, block, tsize, tpw) ? tsize * entry : tsize * entry + 1;
 }
 
 // Squared Euclidean distance in FP32 with a fixed rounding sequence:
 // t0*t0, then fma(tj, tj, acc).  No other contraction is allowed here.
-template <int N>
-__device__ __forceinline__ float dist2(const float (&x)[N], const float *e) {
+template <int N, int WS = 1>
+__device__ __forceinline__ float dist2(const float (&x)[N], const float *e, int ws = WS) {
 #pragma clang fp contract(off)
   float t = x[0] - e[0];
   float acc = t * t;
 #pragma unroll
   for (int j = 1; j < N; ++j) {
-    const float u = x[j] - e[j];
+    const float u = x[j] - e[j * ws];
     acc = __builtin_fmaf(u, u, acc);
   }
   return acc;
 }
 
-template <class R, int LEVEL>
+template <class R, int LEVEL, bool kInterleaved>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k_iact(KArgs a, int tsize, float theta,
                                                                                        int tpw) {
   extern __shared__ float lds[];
@@ -370,7 +375,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
   const int wib = threadIdx.x >> 6;
   const int lpt = kWave / tpw;  // lanes per table
   const int tab_in_wave = lane / lpt;
-  float *tab = lds + ((size_t)wib * tpw + tab_in_wave) * iact_table_stride(E, blockDim.x, tsize, tpw);
+  // word j of entry e of this lane's table: tab[(e * E + j) * ws]
+  const int ws = kInterleaved ? tpw : 1;
+  float *tab = kInterleaved ? lds + (size_t)wib * tpw * tsize * E + tab_in_wave
+                            : lds + ((size_t)wib * tpw + tab_in_wave) * iact_table_stride(E, blockDim.x, tsize, tpw);
   StatsSink sink{a.counters, sums};
   sink.begin();
   BlockTally tally{tally_mem};
@@ -392,7 +400,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
     // read phase: distance to the nearest valid entry of this lane's table
     float md2 = INFINITY;
     if (active)
-      for (int e = 0; e < cnt; ++e) md2 = fminf(md2, dist2<R::kIn>(x, tab + e * E));
+      for (int e = 0; e < cnt; ++e) md2 = fminf(md2, dist2<R::kIn>(x, tab + e * E * ws, ws));
     const bool hit = active && cnt > 0 && md2 < thr2;
     const uint64_t amask = ballot(active);
     const uint64_t vmask = ballot(hit);
@@ -408,9 +416,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
       // the identical FP32 distances)
       int arg = 0;
       for (int e = cnt - 1; e >= 0; --e)
-        if (dist2<R::kIn>(x, tab + e * E) == md2) arg = e;
+        if (dist2<R::kIn>(x, tab + e * E * ws, ws) == md2) arg = e;
 #pragma unroll
-      for (int o = 0; o < R::kOut; ++o) y[o] = tab[arg * E + R::kIn + o];
+      for (int o = 0; o < R::kOut; ++o) y[o] = tab[(arg * E + R::kIn + o) * ws];
     }
     if (computes) R::eval(x, y);
     if (active) store_outputs<R>(a, i, y);
@@ -424,11 +432,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
       const uint64_t mine = cand & segmask;
       if (mine) {
         if (lane == lowest_lane(mine)) {
-          float *slot = tab + (ins % tsize) * E;
+          float *slot = tab + (ins % tsize) * E * ws;
 #pragma unroll
-          for (int j = 0; j < R::kIn; ++j) slot[j] = x[j];
+          for (int j = 0; j < R::kIn; ++j) slot[j * ws] = x[j];
 #pragma unroll
-          for (int o = 0; o < R::kOut; ++o) slot[R::kIn + o] = y[o];
+          for (int o = 0; o < R::kOut; ++o) slot[(R::kIn + o) * ws] = y[o];
         }
         cnt = cnt < tsize ? cnt + 1 : tsize;
         ins += 1;
@@ -802,11 +810,16 @@ struct IactL {
   template <class R>
   hipError_t go() const {
     const size_t lds = (size_t)iact_lds_bytes(c.region, c.block, t, tpw);
+    if (iact_interleaved(entry_floats<R>(), c.block, t, tpw)) return launch<R, true>(lds);
+    return launch<R, false>(lds);
+  }
+  template <class R, bool kIl>
+  hipError_t launch(size_t lds) const {
     const dim3 g = grid_for(a, c.block), b(c.block);
     switch (level) {
-      case kThread: hipLaunchKernelGGL((k_iact<R, kThread>), g, b, lds, c.stream, a, t, thr, tpw); break;
-      case kWaveLvl: hipLaunchKernelGGL((k_iact<R, kWaveLvl>), g, b, lds, c.stream, a, t, thr, tpw); break;
-      default: hipLaunchKernelGGL((k_iact<R, kBlock>), g, b, lds, c.stream, a, t, thr, tpw); break;
+      case kThread: hipLaunchKernelGGL((k_iact<R, kThread, kIl>), g, b, lds, c.stream, a, t, thr, tpw); break;
+      case kWaveLvl: hipLaunchKernelGGL((k_iact<R, kWaveLvl, kIl>), g, b, lds, c.stream, a, t, thr, tpw); break;
+      default: hipLaunchKernelGGL((k_iact<R, kBlock, kIl>), g, b, lds, c.stream, a, t, thr, tpw); break;
     }
     return hipGetLastError();
   }

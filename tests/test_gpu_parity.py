@@ -89,6 +89,10 @@ IACT_CASES = [
     ("thread_tpw1", lambda: inputs.periodic(30000, 8, jitter=1e-3), 8, 8, 0.1, 1, "thread"),
     ("wave_tpw4", lambda: inputs.periodic(65536, 8, jitter=1e-4), 16, 4, 0.05, 4, "wave"),
     ("block_tpw2", lambda: inputs.periodic(65536, 8, jitter=1e-3), 16, 8, 0.08, 2, "block"),
+    # padded tables would overflow 64 KiB of LDS: interleaved word by word
+    ("thread_tpw64_t8", lambda: inputs.periodic(65536, 8, jitter=1e-4), 16, 8, 0.05, 64, "thread"),
+    ("wave_tpw32_t16", lambda: inputs.periodic(65536, 16, jitter=1e-4), 16, 16, 0.05, 32, "wave"),
+    ("block_tpw64_t8", lambda: inputs.periodic(65536, 8, jitter=1e-3), 16, 8, 0.08, 64, "block"),
     ("table32", lambda: inputs.periodic(65536, 32, jitter=1e-4), 64, 32, 0.05, 1, "wave"),
     ("table1", lambda: inputs.constant(5000), 7, 1, 0.05, 1, "wave"),
 ]
