@@ -101,6 +101,8 @@ def test_unsupported_requests():
     # 64 tables of 32 entries for 12 outputs per wave exceed the LDS budget
     expect(hpac.HPAC_EUNSUPPORTED, hpac.hpac_iact, table_size=32, threshold=0.1, tables_per_wave=64,
            **io(outputs=[FAKE] * 12))
+    # price tables interleaved at 64 per wave: 8 entries fill 64 KiB exactly, 9 do not
+    expect(hpac.HPAC_EUNSUPPORTED, hpac.hpac_iact, table_size=9, threshold=0.1, tables_per_wave=64, **io())
     # the Jacobian region takes FP32 columns only; the FP16 body does not take BF16 columns
     args = io()
     d = hpac.make_io(args["inputs"], [FAKE] * 12, n=args["n"], items_per_lane=4, region=hpac.REGION_BS_PRICE_GRAD)
