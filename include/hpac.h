@@ -44,7 +44,7 @@ extern "C" {
 typedef int32_t hpac_status;
 #define HPAC_OK 0
 #define HPAC_EINVAL (-1)       /* an argument is out of range or NULL       */
-#define HPAC_EUNSUPPORTED (-2) /* valid request this build does not provide */
+#define HPAC_EUNSUPPORTED (-2) /* valid request the library does not provide */
 #define HPAC_EHIP (-3)         /* the HIP runtime reported an error         */
 
 /* Regions.  Inputs and outputs are structure-of-arrays columns of n
@@ -195,8 +195,8 @@ hpac_status hpac_bs_adjoint(int64_t n, const void *const *in, const float *grad_
 /* ------------------------------------------------------------------------
  * MLP surrogate: a further approximation technique for HPAC_REGION_BS_PRICE
  * (a learned model standing in for the region inside the box it was trained
- * on; the exact region is the fallback outside it and the judge of its
- * error).  Network 5 -> 64 -> 64 -> 2, GELU (tanh form) on both hidden
+ * on; the exact region is the fallback outside it and the yardstick of
+ * its error).  Network 5 -> 64 -> 64 -> 2, GELU (tanh form) on both hidden
  * layers.  Parameters: one device array of HPAC_MLP_NUM_PARAMS floats,
  *   W1[64][5], b1[64], W2[64][64], b2[64], W3[2][64], b3[2]
  * (row = output unit), kept in FP32; the kernels use the weights rounded to
