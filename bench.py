@@ -50,8 +50,10 @@ VALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=20)
-    p.add_argument("--warmup", type=int, default=3)
+    # the part runs below its working clocks for the first tens of ms of work
+    # after idling: 100 warm-up steps are about 40 ms, 200 timed ones 75 ms
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=100)
     p.add_argument("--n", type=int, default=1 << 24)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-structured", action="store_true")
@@ -730,6 +732,7 @@ def main():
     res = run_workload(torch, hpac, x_copies, n, args.steps, args.warmup)
     tech = summarize(res, n)
     ms_per_step = res["total_ms"] / args.steps
+    leg_steps = max(min(args.steps // 2, 10), 3)  # timed steps of the further legs
     items_per_step = n * len(TECHS)
     value = items_per_step / (ms_per_step * 1e-3)
 
@@ -780,7 +783,7 @@ def main():
             print("[bench] structured-locality variant %s" % vname, file=sys.stderr, flush=True)
             xs = inputs.periodic(n, period, jitter=1e-3)
             xs_copies = [[torch.from_numpy(col).to(dev) for col in xs] for _ in range(3)]
-            rs = run_workload(torch, hpac, xs_copies, n, max(args.steps // 2, 3), 2)
+            rs = run_workload(torch, hpac, xs_copies, n, leg_steps, 2)
             ts = summarize(rs, n)
             structured[vname] = {
                 "workload": desc + " (structured-locality variant, not a paper workload)",
@@ -802,12 +805,12 @@ def main():
     greeks = None
     if not args.no_structured:
         print("[bench] greeks", file=sys.stderr, flush=True)
-        greeks = greeks_leg(torch, hpac, x_copies[0], n, max(args.steps // 2, 3))
+        greeks = greeks_leg(torch, hpac, x_copies[0], n, leg_steps)
 
     precision = None
     if not args.no_structured:
         print("[bench] precision variants", file=sys.stderr, flush=True)
-        precision = precision_leg(torch, hpac, x_copies[0], n, max(args.steps // 2, 3))
+        precision = precision_leg(torch, hpac, x_copies[0], n, leg_steps)
 
     sur = hydro = hier = bo = None
     if not args.no_structured:

@@ -65,6 +65,11 @@ def short_name(name):
 
 
 BS_KERNELS = ("k_exact", "k_iact", "k_taf", "k_taf_wave", "k_perfo", "k_perfo_dense")
+# the kernel each technique of the benchmark step launches (trace names)
+STEP_KERNELS = {"exact": "hpac::k_exact<hpac::RegionBSPrice, false>",
+                "iact": "hpac::k_iact<hpac::RegionBSPrice, 1, false>",
+                "taf": "hpac::k_taf_wave<hpac::RegionBSPrice, 4>",
+                "perfo": "hpac::k_perfo_dense<hpac::RegionBSPrice>"}
 
 
 def _is_bs(name):
@@ -98,6 +103,15 @@ def trace_summary(stats_csv, trace_csv, bench_json, out_txt, command):
     lines += ["", "per-dispatch durations (us), launch order:", ""]
     for k, v in per.items():
         lines.append("    %s: %s" % (k, " ".join("%.0f" % d for d in v)))
+    # the step runs first: dispatches W .. W+K-1 of each step kernel are its timed region
+    w, k = int(bench.get("warmup", 0)), int(bench.get("steps", 0))
+    lines += ["", "timed region of the step (dispatches %d..%d of each kernel), rocprofv3 average beside the "
+              "HIP-event average of the same launches, us:" % (w, w + k - 1), ""]
+    for t, name in STEP_KERNELS.items():
+        d = per.get(name, [])[w:w + k]
+        if d and t in bench["techniques"]:
+            lines.append("    %s (%s): %.1f (HIP events %.1f)" % (t, name, sum(d) / len(d),
+                                                                bench["techniques"][t]["ms"] * 1e3))
     rf = bench.get("roofline", {})
     lines += ["", "roofline reported by that run: %s" % json.dumps(rf)]
     open(out_txt, "w").write("\n".join(lines) + "\n")
