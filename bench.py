@@ -181,7 +181,10 @@ def measured_traffic(kernel, workload, launches_bytes):
     return d.get("hbm_bytes_per_launch") if d else None
 
 
-def run_workload(torch, hpac, x_copies, n, steps, warmup, with_stats=True):
+def run_workload(torch, hpac, x_copies, n, steps, warmup, with_stats=True, min_warm_s=0.0):
+    """Time `steps` steps after at least `warmup` untimed ones, and after at
+    least min_warm_s seconds of warm-up work (the part runs below its
+    working clocks for the first tens of ms of work after idling)."""
     dev = x_copies[0][0].device
     outs = {t: [torch.zeros(n, dtype=torch.float32, device=dev) for _ in range(2)] for t in TECHS}
     stream = torch.cuda.current_stream()
@@ -189,9 +192,13 @@ def run_workload(torch, hpac, x_copies, n, steps, warmup, with_stats=True):
     # argument marshalling done once per (technique, input copy)
     prep = {t: [hpac.prepare(TECHS[t][0], xs, outs[t], items_per_lane=TECHS[t][1], block_size=256,
                              stream=stream, **TECHS[t][2]) for xs in x_copies] for t in names}
-    for s in range(warmup):
+    w, tw = 0, time.perf_counter()
+    while w < warmup or time.perf_counter() - tw < min_warm_s:
         for t in names:
-            prep[t][s % len(x_copies)]()
+            prep[t][w % len(x_copies)]()
+        w += 1
+        if w >= warmup:
+            torch.cuda.synchronize()  # host time then follows the GPU's
     torch.cuda.synchronize()
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)] for _ in range(steps)]
     t0 = time.perf_counter()
@@ -210,7 +217,7 @@ def run_workload(torch, hpac, x_copies, n, steps, warmup, with_stats=True):
     wall = time.perf_counter() - t0
     total_ms = start.elapsed_time(stop)
     per = {t: [ev[s][j].elapsed_time(ev[s][j + 1]) for s in range(steps)] for j, t in enumerate(names)}
-    res = {"total_ms": total_ms, "wall_s": wall, "host_enqueue_s": host_s,
+    res = {"total_ms": total_ms, "wall_s": wall, "host_enqueue_s": host_s, "warmup_steps_run": w,
            "per_kernel_ms": {t: sum(v) / len(v) for t, v in per.items()},
            "per_kernel_median_ms": {t: sorted(v)[len(v) // 2] for t, v in per.items()},
            "per_kernel_min_ms": {t: min(v) for t, v in per.items()}}
@@ -729,7 +736,7 @@ def main():
         pmc_probe(torch, hpac, x_copies, n)
         return
     print("[bench] timing %d steps after %d warmup" % (args.steps, args.warmup), file=sys.stderr, flush=True)
-    res = run_workload(torch, hpac, x_copies, n, args.steps, args.warmup)
+    res = run_workload(torch, hpac, x_copies, n, args.steps, args.warmup, min_warm_s=0.05)
     tech = summarize(res, n)
     ms_per_step = res["total_ms"] / args.steps
     leg_steps = max(min(args.steps // 2, 10), 3)  # timed steps of the further legs
@@ -837,6 +844,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "warmup_steps_run": res["warmup_steps_run"],
         "ms_per_step": ms_per_step,
         "higher_is_better": True,
         "scaling": "weak",

@@ -104,7 +104,7 @@ def trace_summary(stats_csv, trace_csv, bench_json, out_txt, command):
     for k, v in per.items():
         lines.append("    %s: %s" % (k, " ".join("%.0f" % d for d in v)))
     # the step runs first: dispatches W .. W+K-1 of each step kernel are its timed region
-    w, k = int(bench.get("warmup", 0)), int(bench.get("steps", 0))
+    w, k = int(bench.get("warmup_steps_run", bench.get("warmup", 0))), int(bench.get("steps", 0))
     lines += ["", "timed region of the step (dispatches %d..%d of each kernel), rocprofv3 average beside the "
               "HIP-event average of the same launches, us:" % (w, w + k - 1), ""]
     for t, name in STEP_KERNELS.items():
