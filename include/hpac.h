@@ -144,7 +144,11 @@ hpac_status hpac_exact(const hpac_region_io *io);
  *             is below threshold*threshold (FP32).  Nearest: lowest slot
  *             among equal distances.
  * tables_per_wave: tables shared by 64 / tables_per_wave consecutive lanes
- *             (the tPerWarp clause argument); must divide 64.
+ *             (the tPerWarp clause argument); must divide 64.  The tables
+ *             of a workgroup live in its LDS and must fit in 64 KiB
+ *             (HPAC_EUNSUPPORTED otherwise); with many tables per wave,
+ *             smaller workgroups (io->block_size) let more of them share a
+ *             CU and run faster.
  * level:      HPAC_LEVEL_*.
  * Approximate lanes return their nearest entry's outputs without evaluating
  * the region.  Write phase: in each table, among its lanes that evaluated
