@@ -503,6 +503,12 @@ def hierarchy_and_ipt_leg(torch, hpac, n):
                             dict(table_size=8, threshold=0.05, tables_per_wave=tpw, level="wave"), ex)
         r["speedup_vs_exact"] = exact_ms / r["ms"]
         tables[str(tpw)] = r
+    # one table per lane fills a 256-lane workgroup's 64 KiB of LDS (two per
+    # CU, 8 waves); 64-lane workgroups take 16 KiB (ten per CU, 10 waves)
+    r = technique_point(torch, hpac, copies, n, "iact", 16,
+                        dict(table_size=8, threshold=0.05, tables_per_wave=64, level="wave", block_size=64), ex)
+    r["speedup_vs_exact"] = exact_ms / r["ms"]
+    tables["64_block64"] = r
     res["iact_tables_per_wave"] = {"variant": "lane_periodic_64", "params": dict(table_size=8, threshold=0.05),
                                    "items_per_lane": 16, "exact_ms": exact_ms, "tables_per_wave": tables}
     del copies
