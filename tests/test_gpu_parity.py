@@ -101,11 +101,25 @@ IACT_CASES = [
 @pytest.mark.parametrize("case", IACT_CASES, ids=[c[0] for c in IACT_CASES])
 def test_iact_matches_oracle(case):
     name, mk, ipt, t, theta, tpw, level = case
-    block = 256
     say("iact", name)
-    x = mk()
+    check_iact(name, mk(), ipt, t, theta, tpw, level, 256)
+
+
+@pytest.mark.parametrize("tpw,t,level,block", [(64, 8, "wave", 64), (64, 8, "thread", 128), (32, 16, "wave", 64),
+                                               (1, 8, "wave", 64), (16, 8, "thread", 192)])
+def test_iact_block_sizes_match_oracle(tpw, t, level, block):
+    """At thread and wave level the workgroup size changes only how many
+    tables share its LDS (padded or interleaved layout) and the occupancy:
+    decisions and outputs stay the oracle's."""
+    say("iact tpw %d t %d %s block %d" % (tpw, t, level, block))
+    x = inputs.periodic(65536, 16 if t == 16 else 8, jitter=1e-4)
+    check_iact("block%d" % block, x, 16, t, 0.05, tpw, level, block)
+
+
+def check_iact(name, x, ipt, t, theta, tpw, level, block):
     n = x.shape[1]
-    y, tr, cnt = run("iact", to_dev(x), 2, ipt, table_size=t, threshold=theta, tables_per_wave=tpw, level=level)
+    y, tr, cnt = run("iact", to_dev(x), 2, ipt, block_size=block, table_size=t, threshold=theta, tables_per_wave=tpw,
+                     level=level)
     yv, sv = oracle.region_values_f32out(x)
     ora = oracle.iact(x, yv, sv, ipt, t, theta, tables_per_wave=tpw, group=group_of(level, block),
                       out_init=np.full_like(yv, SENTINEL))
