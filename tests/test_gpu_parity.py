@@ -168,11 +168,24 @@ def taf_band(theta):
 def test_taf_matches_oracle(case):
     name, mk, ipt, h, p, theta, level = case
     say("taf", name)
-    x = mk()
+    check_taf(name, mk(), ipt, h, p, theta, level, 256)
+
+
+@pytest.mark.parametrize("level,block", [("wave", 64), ("wave", 192), ("thread", 128), ("block", 128), ("block", 192)])
+def test_taf_block_sizes_match_oracle(level, block):
+    """The workgroup size is the decision group at block level (groups of
+    128 or 192 lanes, the last one ragged) and only a launch shape at the
+    other levels."""
+    say("taf %s block %d" % (level, block))
+    check_taf("%s_block%d" % (level, block), inputs.periodic(65536, 8, jitter=1e-3), 16, 3, 2, 0.006, level, block)
+
+
+def check_taf(name, x, ipt, h, p, theta, level, block):
     n = x.shape[1]
-    y, tr, cnt = run("taf", to_dev(x), 2, ipt, history_size=h, prediction_size=p, rsd_threshold=theta, level=level)
+    y, tr, cnt = run("taf", to_dev(x), 2, ipt, block_size=block, history_size=h, prediction_size=p,
+                     rsd_threshold=theta, level=level)
     yv, sv = oracle.region_values_f32out(x)
-    ora = oracle.taf(yv, sv, ipt, h, p, theta, band=taf_band(theta), group=group_of(level, 256),
+    ora = oracle.taf(yv, sv, ipt, h, p, theta, band=taf_band(theta), group=group_of(level, block),
                      out_init=np.full_like(yv, SENTINEL))
     gdec, f = trace_dec(tr)
     odec = ora["dec"]
@@ -235,6 +248,26 @@ def test_perfo_matches_oracle(case):
     assert np.all(y[:, skipped] == SENTINEL), "dropped items must keep their previous contents"
     check_outputs(y, ora["out"], ora["scale"], mask=~skipped, what="perfo " + name)
     assert cnt[0] == n and cnt[1] == int(skipped.sum())
+
+
+@pytest.mark.parametrize("block", [64, 128, 192])
+@pytest.mark.parametrize("traced", [True, False])
+def test_perfo_block_sizes_match_oracle(block, traced):
+    """Herded perforation at other workgroup sizes, per-unit (traced) and
+    dense kernels."""
+    n, ipt = 40000, 20
+    x = inputs.portfolio(n, 1024)
+    y, tr, cnt = run("perfo", to_dev(x), 2, ipt, block_size=block, trace=traced, counters=traced, kind="small",
+                     param=10, offset=0)
+    yv, sv = oracle.region_values_f32out(x)
+    ora = oracle.perfo(yv, sv, ipt, 0, 10, 0, out_init=np.full_like(yv, SENTINEL))
+    skipped = ora["out"][0] == SENTINEL
+    assert np.all(y[:, skipped] == SENTINEL)
+    check_outputs(y, ora["out"], ora["scale"], mask=~skipped, what="perfo block %d" % block)
+    if traced:
+        gdec, _ = trace_dec(tr)
+        assert np.array_equal(gdec, ora["dec"])
+        assert cnt[0] == n and cnt[1] == int(skipped.sum())
 
 
 DENSE_CASES = [
