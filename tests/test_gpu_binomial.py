@@ -172,6 +172,20 @@ def test_dense_perforation_matches_traced(kind, param, ipt, offset):
     assert np.array_equal(yd, yt)
 
 
+@pytest.mark.parametrize("block", [64, 128, 192])
+def test_block_size_changes_nothing(block):
+    """Each wavefront prices and decides alone, so the units per workgroup
+    change no output, trace word or counter (the 256-lane launch is checked
+    against the oracle above)."""
+    x = inputs.periodic(6000, 64, jitter=1e-3)
+    for fn, kw in ((hpac.hpac_bo_exact, {}), (hpac.hpac_bo_iact, dict(table_size=4, threshold=0.05)),
+                   (hpac.hpac_bo_taf, dict(history_size=2, prediction_size=2, rsd_threshold=0.02)),
+                   (hpac.hpac_bo_perfo, dict(kind="small", param=3))):
+        y0, t0, c0 = run(fn, x, 64, 4, **kw)
+        y1, t1, c1 = run(fn, x, 64, 4, block_size=block, **kw)
+        assert np.array_equal(y1, y0) and np.array_equal(t1, t0) and np.array_equal(c1, c0)
+
+
 def test_thresholds_zero_collapse_to_exact():
     x = inputs.periodic(4096, 8, jitter=1e-4)
     ye, _, _ = run(hpac.hpac_bo_exact, x, 64, 8)
