@@ -120,6 +120,20 @@ def test_iact_memoizes_prices_and_gradients(case):
     say("  approx lanes %.4f" % (cnt[1] / x.shape[1]))
 
 
+@pytest.mark.parametrize("block", [64, 192])
+def test_iact_grad_block_sizes_match_oracle(block):
+    """The price-and-Jacobian tables at other workgroup sizes (more or fewer
+    20-float-entry tables per workgroup's LDS): same decisions and outputs."""
+    x = inputs.periodic(65536, 2, jitter=1e-3)
+    y, tr, cnt = run("iact", to_dev(x), 12, 16, block_size=block, region=hpac.REGION_BS_PRICE_GRAD, table_size=16,
+                     threshold=0.05)
+    yv, sv, _ = grad_region_reference(x)
+    ora = oracle.iact(x, yv, sv, 16, 16, 0.05, out_init=np.full_like(yv, SENTINEL))
+    gdec, f = trace_dec(tr)
+    assert np.array_equal(gdec, ora["dec"])
+    check_outputs(y, ora["out"], ora["scale"], what="iact grad block %d" % block)
+
+
 def test_vjp_contracts_the_saved_jacobian():
     n = 100003
     x = inputs.portfolio(n, 1024)

@@ -121,6 +121,18 @@ def test_taf_and_perforation_on_half_columns(dtype):
     assert np.all(yp[:, ~kept] == 0)
 
 
+@pytest.mark.parametrize("region,dtype", [(hpac.REGION_BS_PRICE_F16, hpac.F16), (hpac.REGION_BS_PRICE_BF16, hpac.BF16),
+                                          (hpac.REGION_BS_PRICE, hpac.F16)])
+@pytest.mark.parametrize("block", [64, 192])
+def test_half_paths_do_not_depend_on_block_size(region, dtype, block):
+    """The half-precision bodies and columns give the same bits at any
+    workgroup size (checked against the oracle at 256 lanes above)."""
+    x = inputs.portfolio(30001, 1024)
+    y0, _ = run_typed(hpac.hpac_exact, x, region, dtype, ipt=2)
+    y1, _ = run_typed(hpac.hpac_exact, x, region, dtype, ipt=2, block_size=block)
+    assert np.array_equal(y1, y0)
+
+
 def test_prepared_launch_keeps_its_columns_alive():
     """A prepared launch built from temporary tensors (here half-precision
     copies) must keep them alive: replaying it after the temporaries went out
