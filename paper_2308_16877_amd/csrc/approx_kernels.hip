@@ -750,17 +750,25 @@ struct ExactL {
 
 hipError_t launch_exact(const LaunchCfg &c, const KArgs &a) { return with_region(c.region, c.dtype, ExactL{c, a}); }
 
+// A dispatch's grid size is a 32-bit count of lanes.
+constexpr int64_t kMaxGridLanes = 0xFFFFFFFFll;
+
 struct PerfoL {
   const LaunchCfg &c;
   const KArgs &a;
   int kind, param, offset;
+  // the per-(wave, step) kernel on at most kCountedGrid workgroups
+  template <class R>
+  hipError_t counted_launch() const {
+    hipLaunchKernelGGL((k_perfo<R>), counted_grid(a, c.block), dim3(c.block), 0, c.stream, a, kind, param, offset);
+    return hipGetLastError();
+  }
   template <class R>
   hipError_t go() const {
-    // the dense paths launch up to ceil(n / block) workgroups
-    if (a.trace || a.counters || param == 0 || (a.n + c.block - 1) / c.block + a.ipt > 2147483647) {
-      hipLaunchKernelGGL((k_perfo<R>), counted_grid(a, c.block), dim3(c.block), 0, c.stream, a, kind, param, offset);
-      return hipGetLastError();
-    }
+    // the dense paths launch one lane per kept item, unless that grid
+    // would exceed the dispatch's 32-bit lane count
+    auto counted = [&] { return counted_launch<R>(); };
+    if (a.trace || a.counters || param == 0) return counted();
     if (kind == kIni || kind == kFini) {
       // a contiguous kept range: the exact kernel over it, one item per lane
       const int64_t cut = ((int64_t)param * a.n) / 100;
@@ -773,6 +781,7 @@ struct PerfoL {
       for (int j = 0; j < R::kIn; ++j) b.in[j] = (const char *)a.in[j] + lo * esz;
       for (int o = 0; o < R::kOut; ++o) b.out[o] = (char *)a.out[o] + lo * esz;
       if (b.n == 0) return hipSuccess;
+      if ((int64_t)grid_for(b, c.block).x * c.block > kMaxGridLanes) return counted();
       hipLaunchKernelGGL((k_exact<R, false>), grid_for(b, c.block), dim3(c.block), 0, c.stream, b);
       return hipGetLastError();
     }
@@ -791,6 +800,7 @@ struct PerfoL {
     }
     if (kept == 0) return hipSuccess;
     const int64_t bps = (a.L + c.block - 1) / c.block;
+    if (kept * bps * c.block > kMaxGridLanes) return counted();
     hipLaunchKernelGGL((k_perfo_dense<R>), dim3((unsigned)(kept * bps)), dim3(c.block), 0, c.stream, a, (int)bps,
                        M, kept_per_period, special, kind == kLarge ? 1 : 0);
     return hipGetLastError();

@@ -336,6 +336,10 @@ static void bo_go_h(const BoArgs &a, int block, hipStream_t s) {
         kept += a.kind == 0 ? pos != b.special : pos == b.special;
       }
       if (kept == 0) return;
+      if (kept * a.L * 64 > 0xFFFFFFFFll) {  // beyond a 32-bit grid: one unit per lane group, as traced
+        hipLaunchKernelGGL((k_binomial<C, TECH, 1>), dim3((unsigned)(a.L * 64 / block)), dim3(block), 0, s, a);
+        return;
+      }
       hipLaunchKernelGGL((k_binomial<C, 4, 1>), dim3((unsigned)(kept * a.L * 64 / block)), dim3(block), 0, s, b);
       return;
     }
@@ -347,6 +351,10 @@ static void bo_go_h(const BoArgs &a, int block, hipStream_t s) {
     if (b.n == 0) return;
     b.ipt = 1;
     b.L = bo_units(b.n, 1);
+    if (b.L * 64 > 0xFFFFFFFFll) {  // beyond a 32-bit grid: the caller's units, as traced
+      hipLaunchKernelGGL((k_binomial<C, TECH, 1>), dim3((unsigned)(a.L * 64 / block)), dim3(block), 0, s, a);
+      return;
+    }
     for (int j = 0; j < 5; ++j) b.in[j] = a.in[j] + lo;
     for (int o = 0; o < 2; ++o) b.out[o] = a.out[o] + lo;
     hipLaunchKernelGGL((k_binomial<C, 0, 1>), dim3((unsigned)(b.L * 64 / block)), dim3(block), 0, s, b);

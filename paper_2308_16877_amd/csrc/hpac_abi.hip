@@ -40,7 +40,8 @@ bool region_shape(int region, RegionShape *s) {
 
 constexpr int64_t kMaxItems = (int64_t)1 << 40;
 constexpr int32_t kMaxIpt = 65536;
-constexpr int64_t kMaxBlocks = 2147483647;
+// A dispatch's grid size is a 32-bit count of work-items.
+constexpr int64_t kMaxWorkItems = 0xFFFFFFFFll;
 
 int64_t num_lanes(int64_t n, int32_t ipt) {
   const int64_t per = (n + ipt - 1) / ipt;
@@ -76,9 +77,9 @@ hpac_status check_io(const char *fn, const hpac_region_io *io, hpac::KArgs *a, h
       if ((uintptr_t)io->out[o] % align) return fail(HPAC_EINVAL, "%s: output column %d is misaligned", fn, o);
     }
   }
-  if ((num_lanes(io->n, io->items_per_lane) + block - 1) / block > kMaxBlocks)
-    return fail(HPAC_EINVAL, "%s: %lld items at %d items per lane need more than 2^31-1 workgroups; raise items_per_lane",
-                fn, (long long)io->n, io->items_per_lane);
+  if ((num_lanes(io->n, io->items_per_lane) + block - 1) / block * block > kMaxWorkItems)
+    return fail(HPAC_EINVAL, "%s: %lld items at %d items per lane need a grid of more than 2^32-1 lanes; raise "
+                "items_per_lane", fn, (long long)io->n, io->items_per_lane);
   if ((uintptr_t)io->trace % 4) return fail(HPAC_EINVAL, "%s: trace is not 4-byte aligned", fn);
   if ((uintptr_t)io->counters % 8) return fail(HPAC_EINVAL, "%s: counters are not 8-byte aligned", fn);
   for (int j = 0; j < hpac::kMaxIn; ++j) a->in[j] = j < rs.n_in && io->n > 0 ? io->in[j] : nullptr;
@@ -109,6 +110,9 @@ hpac_status check_bo(const char *fn, const hpac_region_io *io, int32_t steps, in
     return fail(HPAC_EINVAL, "%s: items_per_lane = %d out of range [1, %d]", fn, io->items_per_lane, kMaxIpt);
   const int b = io->block_size == 0 ? 256 : io->block_size;
   if (b < 64 || b > 256 || b % 64) return fail(HPAC_EINVAL, "%s: block_size = %d must be 64, 128, 192 or 256", fn, b);
+  if (hpac::bo_units(io->n, io->items_per_lane) * 64 > kMaxWorkItems)
+    return fail(HPAC_EINVAL, "%s: %lld options at %d per unit need a grid of more than 2^32-1 lanes; raise "
+                "items_per_lane", fn, (long long)io->n, io->items_per_lane);
   if (steps < 1 || hpac::bo_nodes_per_lane(steps) == 0)
     return fail(HPAC_EINVAL, "%s: steps = %d out of range [1, 1023]", fn, steps);
   if (american != 0 && american != 1) return fail(HPAC_EINVAL, "%s: american must be 0 or 1", fn);
@@ -321,7 +325,8 @@ hpac_status hpac_mlp_grad(int64_t batch, const float *const *x, const float *con
                           const hpac_mlp_norm *norm, int64_t loss_count, float *grad_partials, float *loss_partials,
                           void *stream) {
   const char *fn = "hpac_mlp_grad";
-  if (batch < 0 || batch > ((int64_t)1 << 31) * 64) return fail(HPAC_EINVAL, "%s: batch out of range", fn);
+  if (batch < 0 || (batch + 63) / 64 * 64 > kMaxWorkItems)
+    return fail(HPAC_EINVAL, "%s: batch = %lld out of range [0, 2^32 - 64]", fn, (long long)batch);
   if (loss_count < 1) return fail(HPAC_EINVAL, "%s: loss_count must be >= 1", fn);
   hpac::MlpGradArgs a = {};
   hpac_status s = copy_norm(fn, norm, a.in_center, a.in_scale, a.out_mean, a.out_scale);

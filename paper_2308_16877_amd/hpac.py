@@ -159,6 +159,31 @@ def _addr(t):
     return t.data_ptr()
 
 
+# element types a device buffer argument may have, by kind
+_KINDS = {"u32": ("int32", "uint32"), "u64": ("int64", "uint64"), "i32": ("int32",), "i8": ("int8", "uint8"),
+          "f32": ("float32",), "f64": ("float64",), "bytes": None}
+
+
+def _check_buf(t, need, kind, what):
+    """A device buffer the kernels write or read beyond the columns: a torch
+    tensor must be contiguous, of the element type `kind` and hold at least
+    `need` elements (bytes for kind "bytes"), since a short buffer would be
+    written out of bounds on the device.  Raw addresses (ints) are the
+    caller's responsibility; None passes (optional buffers)."""
+    if t is None or isinstance(t, int):
+        return
+    allowed = _KINDS[kind]
+    dt = str(t.dtype).replace("torch.", "")
+    if allowed is not None and dt not in allowed:
+        raise ValueError("%s must have element type %s, got %s" % (what, " or ".join(allowed), dt))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    have = t.numel() * (t.element_size() if allowed is None else 1)
+    if have < need:
+        raise ValueError("%s holds %d %s, the call needs at least %d" % (
+            what, have, "bytes" if allowed is None else "elements", need))
+
+
 def _dtype_code(t):
     import torch
     return {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}.get(t.dtype)
@@ -194,6 +219,15 @@ def make_io(inputs, outputs, n=None, region=None, items_per_lane=1, block_size=0
         dtype = F32 if first is None else _dtype_code(first)
     for c in inputs + outputs:
         _check_column(c, n, dtype)
+    if trace is not None and not isinstance(trace, int):
+        if region == REGION_BINOMIAL:
+            need = hpac_bo_units(n, items_per_lane) * items_per_lane
+        else:
+            need = hpac_trace_entries(n, items_per_lane)
+        if need < 0:
+            raise ValueError("n = %d or items_per_lane = %d out of range" % (n, items_per_lane))
+        _check_buf(trace, need, "u32", "trace")
+    _check_buf(counters, NUM_COUNTERS, "u64", "counters")
     ins = (ctypes.c_void_p * max(len(inputs), 1))(*[_addr(c) for c in inputs])
     outs = (ctypes.c_void_p * max(len(outputs), 1))(*[_addr(c) for c in outputs])
     io = hpac_region_io(region, dtype, n, ctypes.cast(ins, ctypes.POINTER(ctypes.c_void_p)), len(inputs),
@@ -307,9 +341,12 @@ def hpac_bs_adjoint(inputs, grad_call, grad_put, grad_in, n=None, stream=None):
     _call("hpac_bs_adjoint", lib().hpac_bs_adjoint(n, ip, _addr(grad_call), _addr(grad_put), gp, st))
 
 
-def hpac_surrogate(inputs, outputs, params, norm, box_lo, box_hi, queue, queue_count, stream=None):
+def hpac_surrogate(inputs, outputs, params, norm, box_lo, box_hi, queue, queue_count, stream=None, n=None):
     """Surrogate inference with the exact region as fallback outside the box."""
-    io = make_io(inputs, outputs, region=REGION_BS_PRICE, stream=stream)
+    io = make_io(inputs, outputs, n=n, region=REGION_BS_PRICE, stream=stream)
+    _check_buf(params, MLP_NUM_PARAMS, "f32", "params")
+    _check_buf(queue, io.n, "i32", "queue")
+    _check_buf(queue_count, 1, "i32", "queue_count")
     lo = (ctypes.c_float * 5)(*map(float, box_lo))
     hi = (ctypes.c_float * 5)(*map(float, box_hi))
     _call("hpac_surrogate", lib().hpac_surrogate(ctypes.byref(io), _addr(params), ctypes.byref(norm), lo, hi,
@@ -324,6 +361,10 @@ def hpac_mlp_grad(x, t, params, norm, loss_count, grad_partials, loss_partials, 
     n = x[0].numel() if n is None else n
     for c in list(x) + list(t):
         _check_column(c, n)
+    blocks = hpac_mlp_grad_blocks(n)
+    _check_buf(params, MLP_NUM_PARAMS, "f32", "params")
+    _check_buf(grad_partials, blocks * MLP_NUM_PARAMS, "f32", "grad_partials")
+    _check_buf(loss_partials, blocks, "f32", "loss_partials")
     xp, k1 = _ptr_array(x)
     tp, k2 = _ptr_array(t)
     st = _stream(stream, list(x))
@@ -332,16 +373,22 @@ def hpac_mlp_grad(x, t, params, norm, loss_count, grad_partials, loss_partials, 
 
 
 def hpac_mlp_adam(grad_partials, blocks, params, m, v, lr, beta1, beta2, eps, step, stream=None):
+    _check_buf(grad_partials, blocks * MLP_NUM_PARAMS, "f32", "grad_partials")
+    for t, what in ((params, "params"), (m, "m"), (v, "v")):
+        _check_buf(t, MLP_NUM_PARAMS, "f32", what)
     st = _stream(stream, [params])
     _call("hpac_mlp_adam", lib().hpac_mlp_adam(_addr(grad_partials), blocks, _addr(params), _addr(m), _addr(v),
                                                lr, beta1, beta2, eps, step, st))
 
 
 def hpac_probe_copy(src, dst, nbytes, stream=None):
+    _check_buf(src, nbytes, "bytes", "src")
+    _check_buf(dst, nbytes, "bytes", "dst")
     _call("hpac_probe_copy", lib().hpac_probe_copy(_addr(src), _addr(dst), nbytes, _stream(stream, [src, dst])))
 
 
 def hpac_probe_valu(out, workgroups, iters, scalar_operand, stream=None):
+    _check_buf(out, int(workgroups) * 256, "f32", "out")
     _call("hpac_probe_valu", lib().hpac_probe_valu(_addr(out), int(workgroups), int(iters), int(bool(scalar_operand)),
                                                    _stream(stream, [out])))
 
@@ -398,6 +445,10 @@ def hpac_hydro_init(params, e_origin, state, stream=None):
 
 
 def hpac_hydro_step(params, tech, step, state, dec_eos=None, dec_hg=None, stream=None):
+    if tech.eos_history:
+        _check_buf(dec_eos, hpac_hydro_groups(params.n, tech.eos_level), "i8", "dec_eos")
+    if tech.hg_history:
+        _check_buf(dec_hg, hpac_hydro_groups(params.n, tech.hg_level), "i8", "dec_hg")
     _call("hpac_hydro_step", lib().hpac_hydro_step(ctypes.byref(params), ctypes.byref(tech), int(step),
                                                    ctypes.byref(state), _addr(dec_eos), _addr(dec_hg),
                                                    _torch_stream(stream)))

@@ -107,14 +107,22 @@ def trace_summary(stats_csv, trace_csv, bench_json, out_txt, command):
     w, k = int(bench.get("warmup_steps_run", bench.get("warmup", 0))), int(bench.get("steps", 0))
     lines += ["", "timed region of the step (dispatches %d..%d of each kernel), rocprofv3 average beside the "
               "HIP-event average of the same launches, us:" % (w, w + k - 1), ""]
+    timed = {}
     for t, name in STEP_KERNELS.items():
         d = per.get(name, [])[w:w + k]
         if d and t in bench["techniques"]:
             lines.append("    %s (%s): %.1f (HIP events %.1f)" % (t, name, sum(d) / len(d),
                                                                 bench["techniques"][t]["ms"] * 1e3))
+            kernel = name.split("<")[0].replace("hpac::", "")
+            timed[kernel] = {"technique": t, "trace_name": name, "avg_us": sum(d) / len(d), "dispatches": len(d),
+                             "hip_event_avg_us": bench["techniques"][t]["ms"] * 1e3,
+                             "kernel_source_sha": kernel_source_sha(kernel)}
     rf = bench.get("roofline", {})
     lines += ["", "roofline reported by that run: %s" % json.dumps(rf)]
     open(out_txt, "w").write("\n".join(lines) + "\n")
+    # the timed-region averages, for the benchmark's rocprofv3-based fraction
+    json.dump({"command": command, "timed_region": timed}, open(os.path.splitext(out_txt)[0] + ".json", "w"),
+              indent=1)
 
 
 def _pmc(path, counter):

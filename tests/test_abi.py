@@ -239,3 +239,63 @@ def test_invalid_binomial_arguments_are_rejected():
         lib = hpac.lib()
         desc = hpac.make_io([FAKE] * 5, [FAKE] * 2, n=10, region=hpac.REGION_BS_PRICE, stream=0)
         hpac._call("hpac_bo_exact", lib.hpac_bo_exact(ctypes.byref(desc), 64, 1))
+
+
+def test_grids_beyond_32_bit_lane_counts_are_rejected():
+    """A dispatch counts its lanes in 32 bits: a grid-stride mapping whose
+    grid would exceed 2^32-1 lanes is refused at validation (with a hint to
+    raise items_per_lane), and one just inside is accepted."""
+    E = hpac.HPAC_EINVAL
+    msg = expect(E, hpac.hpac_exact, **io(n=2**32 + 1, items_per_lane=1))
+    assert "items_per_lane" in msg
+    expect(E, hpac.hpac_iact, table_size=8, threshold=0.1, **io(n=2**33, items_per_lane=1))
+    expect(E, hpac.hpac_taf, history_size=4, prediction_size=4, rsd_threshold=0.1, **io(n=2**33, items_per_lane=1))
+    expect(E, hpac.hpac_perfo, kind="small", param=10, **io(n=2**33, items_per_lane=1))
+    # 2^40 items at 256 per lane need 2^32 lanes: one too many
+    expect(E, hpac.hpac_exact, **io(n=2**40, items_per_lane=256))
+    # binomial: 64 lanes per unit
+    expect(E, hpac.hpac_bo_exact, [FAKE] * 5, [FAKE] * 2, 64, n=2**26, items_per_lane=1)
+    # training batches: one lane per sample
+    nm = hpac.make_norm([0] * 5, [1] * 5, [0, 0], [1, 1])
+    expect(E, hpac.hpac_mlp_grad, [FAKE] * 5, [FAKE] * 2, FAKE, nm, 1, FAKE, FAKE, n=2**32)
+
+
+def test_short_or_mistyped_buffers_are_rejected_by_the_binding():
+    """The binding checks every device buffer a kernel writes beyond the
+    columns (trace, counters, the surrogate's queue, training partials):
+    a short one would be written out of bounds on the device."""
+    import torch
+    n, ipt = 1000, 4
+    need = hpac.hpac_trace_entries(n, ipt)
+    with pytest.raises(ValueError, match="trace holds"):
+        hpac.hpac_exact(**io(trace=torch.zeros(need - 1, dtype=torch.int32)))
+    with pytest.raises(ValueError, match="element type"):
+        hpac.hpac_exact(**io(trace=torch.zeros(need, dtype=torch.float32)))
+    with pytest.raises(ValueError, match="counters holds"):
+        hpac.hpac_exact(**io(counters=torch.zeros(3, dtype=torch.int64)))
+    with pytest.raises(ValueError, match="element type"):
+        hpac.hpac_exact(**io(counters=torch.zeros(4, dtype=torch.int32)))
+    # binomial traces have one word per (unit, option of the unit)
+    units = hpac.hpac_bo_units(n, ipt)
+    with pytest.raises(ValueError, match="trace holds"):
+        hpac.hpac_bo_exact([FAKE] * 5, [FAKE] * 2, 64, n=n, items_per_lane=ipt,
+                           trace=torch.zeros(units * ipt - 1, dtype=torch.int32))
+    nm = hpac.make_norm([0] * 5, [1] * 5, [0, 0], [1, 1])
+    lo, hi = [0.0] * 5, [1.0] * 5
+    x, y = [FAKE] * 5, [FAKE] * 2
+    with pytest.raises(ValueError, match="queue holds"):
+        hpac.hpac_surrogate(x, y, FAKE, nm, lo, hi, torch.zeros(n - 1, dtype=torch.int32), FAKE, n=n)
+    with pytest.raises(ValueError, match="params holds"):
+        hpac.hpac_surrogate(x, y, torch.zeros(10), nm, lo, hi, FAKE, FAKE, n=n)
+    with pytest.raises(ValueError, match="queue_count"):
+        hpac.hpac_surrogate(x, y, FAKE, nm, lo, hi, FAKE, torch.zeros(1, dtype=torch.int64), n=n)
+    blocks = hpac.hpac_mlp_grad_blocks(n)
+    with pytest.raises(ValueError, match="grad_partials holds"):
+        hpac.hpac_mlp_grad([FAKE] * 5, [FAKE] * 2, FAKE, nm, n,
+                           torch.zeros(blocks * hpac.MLP_NUM_PARAMS - 1), FAKE, n=n)
+    with pytest.raises(ValueError, match="loss_partials holds"):
+        hpac.hpac_mlp_grad([FAKE] * 5, [FAKE] * 2, FAKE, nm, n, FAKE, torch.zeros(blocks - 1), n=n)
+    with pytest.raises(ValueError, match="m holds"):
+        hpac.hpac_mlp_adam(FAKE, 1, FAKE, torch.zeros(100), FAKE, 1e-3, 0.9, 0.999, 1e-8, 1)
+    with pytest.raises(ValueError, match="dst holds"):
+        hpac.hpac_probe_copy(FAKE, torch.zeros(3, dtype=torch.float32), 16)
