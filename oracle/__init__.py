@@ -60,7 +60,9 @@ def _load():
     lib.or_bs_jacobian.restype = None
     lib.or_bs_jacobian.argtypes = [i64] + [P] * 6
     lib.or_iact.restype = ctypes.c_int
-    lib.or_iact.argtypes = [i64, i32, i32, i32, P, i32, P, P, i32, f32, i32, P, P, P, P, P, P, P]
+    lib.or_iact.argtypes = [i64, i32, i32, i32, P, i32, P, P, i32, f32, i32, P, P, P, P, P, P, P, i32, f64, P]
+    lib.or_adam.restype = None
+    lib.or_adam.argtypes = [i64, i64, P, P, P, P, f64, f64, f64, f64, i32]
     lib.or_taf.restype = ctypes.c_int
     lib.or_taf.argtypes = [i64, i32, i32, i32, P, P, i32, i32, f32, f64, P, P, P, P, P, P, P]
     lib.or_perfo.restype = ctypes.c_int
@@ -156,8 +158,13 @@ def _out_arrays(n_out, n, out_init):
     return out, np.zeros((n_out, n), np.float64)
 
 
-def iact(x, y, s, ipt, table_size, threshold, tables_per_wave=1, group=GROUP_WAVE, out_init=None):
-    """iACT engine over region values y (n_out, n) for inputs x (n_in, n)."""
+def iact(x, y, s, ipt, table_size, threshold, tables_per_wave=1, group=GROUP_WAVE, out_init=None,
+         dist_fp64=False, band=0.0):
+    """iACT engine over region values y (n_out, n) for inputs x (n_in, n).
+    dist_fp64 takes the squared distance and its threshold test in FP64 (the
+    plain definition) instead of FP32 with the fixed rounding order; band > 0
+    marks the (wave, step) records where the other precision could choose
+    differently (`fragile`)."""
     x = _as_f32_cols(x)
     y = _as_f64_cols(y)
     s = _as_f64_cols(s) if s is not None else [np.zeros_like(c) for c in y]
@@ -168,15 +175,30 @@ def iact(x, y, s, ipt, table_size, threshold, tables_per_wave=1, group=GROUP_WAV
     votes = np.empty(W * ipt, np.int16)
     writer = np.empty(W * ipt, np.int16)
     napprox = np.empty(W * ipt, np.int16)
+    fragile = np.empty(W * ipt, np.uint8)
     evals = ctypes.c_int64(0)
     rc = _load().or_iact(n, ipt, group, len(x), _cols(x), len(y), _cols(y), _cols(s),
                          table_size, np.float32(threshold), tables_per_wave,
                          _cols(list(out)), _cols(list(osc)), _ptr(dec), _ptr(votes),
-                         _ptr(writer), _ptr(napprox), ctypes.byref(evals))
+                         _ptr(writer), _ptr(napprox), ctypes.byref(evals), int(bool(dist_fp64)), float(band),
+                         _ptr(fragile) if band > 0 else None)
     if rc != 0:
         raise ValueError("or_iact rejected its arguments")
+    if band <= 0:
+        fragile[:] = 0
     return dict(out=out, scale=osc, dec=dec, votes=votes, writer=writer,
-                napprox=napprox, evals=evals.value, ipt=ipt)
+                napprox=napprox, evals=evals.value, ipt=ipt, fragile=fragile)
+
+
+def adam(partials, w, m, v, lr, beta1, beta2, eps, step):
+    """One Adam step in FP64 on copies of w, m, v (arrays of p); partials is
+    (blocks, p), summed to the gradient.  Returns (w, m, v)."""
+    partials = np.ascontiguousarray(np.atleast_2d(partials), dtype=np.float64)
+    w, m, v = (np.array(a, dtype=np.float64, copy=True) for a in (w, m, v))
+    blocks, p = partials.shape
+    _load().or_adam(p, blocks, _ptr(partials), _ptr(w), _ptr(m), _ptr(v), float(lr), float(beta1), float(beta2),
+                    float(eps), int(step))
+    return w, m, v
 
 
 def taf(y, s, ipt, history_size, prediction_size, threshold, band=0.0, group=GROUP_WAVE, out_init=None):

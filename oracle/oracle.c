@@ -163,25 +163,49 @@ static float or_dist2_f32(const float *a, const float *b, int d) {
   return acc;
 }
 
+/* The plain definition: the squared Euclidean distance in FP64 of the two
+ * FP32 points, summed over the coordinates in order. */
+static double or_dist2_f64(const float *a, const float *b, int d) {
+  double acc = 0.0;
+  for (int j = 0; j < d; ++j) {
+    double u = (double)a[j] - (double)b[j];
+    acc += u * u;
+  }
+  return acc;
+}
+
 #define OR_MAX_IN 8
 #define OR_MAX_OUT 16
 #define OR_MAX_T 64
 
+/* dist_fp64 selects the reading of the distance: 0 = the squared distance,
+ * its threshold and their comparison in FP32 with the fixed rounding order
+ * of or_dist2_f32 (the precision the GPU decides in); 1 = the plain FP64
+ * definition (or_dist2_f64, compared with theta^2 in FP64).  With fragile
+ * != NULL, a (wave, step) is marked where a statistic lies so close to the
+ * point where a choice changes that the other precision could choose
+ * differently: (i) lanes whose distance is within band * theta of theta
+ * could flip their group's majority, (ii) a table's two farthest computing
+ * lanes (writer candidates) are within `band` relative of each other, or
+ * (iii) an approximating lane's two nearest entries with different outputs
+ * are within `band` relative of each other. */
 int or_iact(int64_t n, int32_t ipt, int32_t group, int32_t n_in,
             const float *const *x, int32_t n_out, const double *const *ysrc,
             const double *const *ssrc, int32_t tsize, float theta,
             int32_t tables_per_wave, double *const *out, double *const *oscale,
             int8_t *dec, int16_t *votes, int16_t *writer, int16_t *napprox,
-            int64_t *n_evals) {
+            int64_t *n_evals, int32_t dist_fp64, double band, uint8_t *fragile) {
   if (n_in < 1 || n_in > OR_MAX_IN || n_out < 1 || n_out > OR_MAX_OUT) return -1;
   if (tsize < 1 || tsize > OR_MAX_T) return -1;
   if (tables_per_wave < 1 || OR_WAVE % tables_per_wave) return -1;
   if (group < 1 || (group != 1 && group % OR_WAVE)) return -1;
   int64_t L = or_num_lanes(n, ipt);
   int64_t nwaves = L / OR_WAVE;
-  or_trace tr = {dec, votes, writer, NULL, napprox};
+  or_trace tr = {dec, votes, writer, fragile, napprox};
   or_trace_init(&tr, nwaves * ipt);
-  const float thr2 = theta * theta;
+  const float thr2_f32 = theta * theta;
+  const double thr2_f64 = (double)theta * (double)theta;
+  const double th = (double)theta;
   const int lanes_per_table = OR_WAVE / tables_per_wave;
   /* Decision groups never straddle a work unit: a unit is one wave for
    * thread and wave level, one block of `group` lanes for block level. */
@@ -200,7 +224,8 @@ int or_iact(int64_t n, int32_t ipt, int32_t group, int32_t n_in,
     double *ts = calloc((size_t)ntab * tsize * n_out, sizeof(double));
     int *tcount = calloc(ntab, sizeof(int));
     int64_t *tins = calloc(ntab, sizeof(int64_t));
-    float *md2 = malloc(nl * sizeof(float));
+    double *md2 = malloc(nl * sizeof(double)); /* an FP32 value in FP32 mode */
+    double *sec = malloc(nl * sizeof(double)); /* second-nearest entry with other outputs */
     int *arg = malloc(nl * sizeof(int));
     int *hit = malloc(nl * sizeof(int));
     int *computes = malloc(nl * sizeof(int));
@@ -211,15 +236,29 @@ int or_iact(int64_t n, int32_t ipt, int32_t group, int32_t n_in,
       /* read phase */
       for (int64_t j = 0; j < nl; ++j) {
         int64_t i = l0 + j + (int64_t)k * L;
-        hit[j] = 0; md2[j] = INFINITY; arg[j] = -1; computes[j] = 0;
+        hit[j] = 0; md2[j] = INFINITY; sec[j] = INFINITY; arg[j] = -1; computes[j] = 0;
         if (i >= n) continue;
         int tb = (int)(j / lanes_per_table);
         for (int d = 0; d < n_in; ++d) xi[d] = x[d][i];
         for (int e = 0; e < tcount[tb]; ++e) {
-          float d2 = or_dist2_f32(xi, &tx[((size_t)tb * tsize + e) * n_in], n_in);
+          const float *ex = &tx[((size_t)tb * tsize + e) * n_in];
+          double d2 = dist_fp64 ? or_dist2_f64(xi, ex, n_in) : (double)or_dist2_f32(xi, ex, n_in);
           if (d2 < md2[j]) { md2[j] = d2; arg[j] = e; }
         }
-        hit[j] = tcount[tb] > 0 && md2[j] < thr2;
+        if (fragile && arg[j] >= 0) {
+          /* the nearest entry whose outputs differ from the chosen one's */
+          const double *ya = &ty[((size_t)tb * tsize + arg[j]) * n_out];
+          for (int e = 0; e < tcount[tb]; ++e) {
+            const double *ye = &ty[((size_t)tb * tsize + e) * n_out];
+            int same = 1;
+            for (int o = 0; o < n_out; ++o) same &= ye[o] == ya[o];
+            if (same) continue;
+            const float *ex = &tx[((size_t)tb * tsize + e) * n_in];
+            double d2 = dist_fp64 ? or_dist2_f64(xi, ex, n_in) : (double)or_dist2_f32(xi, ex, n_in);
+            if (d2 < sec[j]) sec[j] = d2;
+          }
+        }
+        hit[j] = tcount[tb] > 0 && (dist_fp64 ? md2[j] < thr2_f64 : (float)md2[j] < thr2_f32);
       }
       /* decision per group, then each lane's path */
       for (int64_t g0 = 0; g0 < nl; g0 += group) {
@@ -230,11 +269,25 @@ int or_iact(int64_t n, int32_t ipt, int32_t group, int32_t n_in,
         if (!act) continue;
         int approx = or_majority(yes, act);
         gdec[g0 / group] = approx;
+        if (fragile && th > 0.0) {
+          /* (i): lanes whose distance lies within band * theta of theta */
+          int near_yes = 0, near_no = 0;
+          for (int64_t j = g0; j < g0 + group && j < nl; ++j) {
+            if (l0 + j + (int64_t)k * L >= n || arg[j] < 0) continue;
+            if (fabs(sqrt(md2[j]) - th) <= band * th) { if (hit[j]) near_yes++; else near_no++; }
+          }
+          int flip = group == 1 ? near_yes + near_no > 0
+                                : or_majority(yes - near_yes, act) != or_majority(yes + near_no, act);
+          for (int64_t wl = g0 / OR_WAVE; flip && wl * OR_WAVE < g0 + group && wl * OR_WAVE < nl; ++wl)
+            fragile[(l0 / OR_WAVE + wl) * ipt + k] = 1;
+        }
         for (int64_t j = g0; j < g0 + group && j < nl; ++j) {
           int64_t i = l0 + j + (int64_t)k * L;
           if (i >= n) continue;
           int tb = (int)(j / lanes_per_table);
           int lane_approx = group == 1 ? hit[j] : approx;
+          if (fragile && lane_approx && arg[j] >= 0 && sqrt(sec[j]) - sqrt(md2[j]) <= band * sqrt(sec[j]))
+            fragile[((l0 + j) / OR_WAVE) * ipt + k] = 1; /* (iii) */
           if (lane_approx && arg[j] >= 0) {
             for (int o = 0; o < n_out; ++o) {
               out[o][i] = ty[((size_t)tb * tsize + arg[j]) * n_out + o];
@@ -254,11 +307,16 @@ int or_iact(int64_t n, int32_t ipt, int32_t group, int32_t n_in,
       int64_t w_first = l0 / OR_WAVE;
       for (int tb = 0; tb < ntab; ++tb) {
         int64_t j0 = (int64_t)tb * lanes_per_table;
-        int64_t best = -1;
+        int64_t best = -1, second = -1;
         for (int64_t j = j0; j < j0 + lanes_per_table; ++j) {
           if (!computes[j]) continue;
-          if (best < 0 || md2[j] > md2[best]) best = j;
+          if (best < 0 || md2[j] > md2[best]) { second = best; best = j; }
+          else if (second < 0 || md2[j] > md2[second]) second = j;
         }
+        /* (ii): two writer candidates at finite distances within band */
+        if (fragile && second >= 0 && isfinite(md2[best]) &&
+            sqrt(md2[best]) - sqrt(md2[second]) <= band * sqrt(md2[best]))
+          fragile[((l0 + j0) / OR_WAVE) * ipt + k] = 1;
         if (best >= 0) {
           int64_t i = l0 + best + (int64_t)k * L;
           int slot = (int)(tins[tb] % tsize);
@@ -291,7 +349,7 @@ int or_iact(int64_t n, int32_t ipt, int32_t group, int32_t n_in,
       }
     }
     free(tx); free(ty); free(ts); free(tcount); free(tins);
-    free(md2); free(arg); free(hit); free(computes); free(gdec);
+    free(md2); free(sec); free(arg); free(hit); free(computes); free(gdec);
   }
   if (n_evals) *n_evals = evals;
   return 0;
@@ -660,3 +718,23 @@ double or_mlp_loss_grad(int64_t n, const double *const *x, const double *const *
 }
 
 double or_mlp_gelu(double x) { return or_gelu(x, 1); }
+
+/* ------------------------------------------------------------------------ */
+/* Adam (Kingma and Ba, "Adam: A Method for Stochastic Optimization",        */
+/* ICLR 2015, Algorithm 1) in FP64: the surrogate's optimiser.  The          */
+/* gradient is the sum of `blocks` partial gradients of p parameters each    */
+/* (partials[b * p + q]); t >= 1 is the step number of the bias correction. */
+/*   m <- beta1 m + (1 - beta1) g;  v <- beta2 v + (1 - beta2) g^2           */
+/*   w <- w - lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps)      */
+/* ------------------------------------------------------------------------ */
+void or_adam(int64_t p, int64_t blocks, const double *partials, double *w, double *m, double *v, double lr,
+             double beta1, double beta2, double eps, int32_t t) {
+  const double c1 = 1.0 - pow(beta1, (double)t), c2 = 1.0 - pow(beta2, (double)t);
+  for (int64_t q = 0; q < p; ++q) {
+    double g = 0.0;
+    for (int64_t b = 0; b < blocks; ++b) g += partials[b * p + q];
+    m[q] = beta1 * m[q] + (1.0 - beta1) * g;
+    v[q] = beta2 * v[q] + (1.0 - beta2) * g * g;
+    w[q] -= lr * (m[q] / c1) / (sqrt(v[q] / c2) + eps);
+  }
+}

@@ -140,6 +140,66 @@ def check_iact(name, x, ipt, t, theta, tpw, level, block):
     say("  approx lanes %.4f  mape gpu %.3g oracle %.3g" % (cnt[1] / n, mg, mo))
 
 
+def flip_wave_inputs():
+    """One wave that stores (S, K) = (10, 10) at step 0 and meets
+    (10.4447126, 10.7893143) at step 1 (T, r, v unchanged): at a threshold
+    of 0.9059726 the FP32 distance test fails and the FP64 one passes."""
+    x = np.tile(np.array([[10.0], [10.0], [1.0], [0.02], [0.3]], np.float32), (1, 128))
+    x[0, 64:], x[1, 64:] = 10.44471263885498, 10.789314270019531
+    return x
+
+
+IACT_FP64_CASES = [
+    # name, input builder, ipt, table, theta, tables/wave, level
+    ("config0", lambda: inputs.portfolio(65536, 1024), 16, 8, 0.05, 1, "wave"),
+    ("periodic8_mixed", lambda: inputs.periodic(65536, 8, jitter=1e-3), 16, 8, 0.08, 1, "wave"),
+    ("periodic2", lambda: inputs.periodic(65536, 2, jitter=1e-3), 16, 8, 0.05, 1, "wave"),
+    ("thread_tpw1", lambda: inputs.periodic(30000, 8, jitter=1e-3), 8, 8, 0.1, 1, "thread"),
+    ("block_tpw2", lambda: inputs.periodic(65536, 8, jitter=1e-3), 16, 8, 0.08, 2, "block"),
+    ("flip", flip_wave_inputs, 2, 2, 0.9059725999832153, 1, "wave"),
+]
+
+
+@pytest.mark.parametrize("case", IACT_FP64_CASES, ids=[c[0] for c in IACT_FP64_CASES])
+def test_iact_against_fp64_distances(case):
+    """The kernels decide on the squared distance in FP32; the oracle here
+    takes the plain FP64 definition instead.  Decisions and writers agree on
+    at least 99.99% of (wave, step) records, and every first disagreement of
+    a wave falls on a record where a distance lies within 1e-5 relative of
+    the threshold (and could flip the vote), two writer candidates or two
+    nearest entries lie within 1e-5 relative of each other: the FP32 reading
+    hides no kernel defect.  Outputs away from such records match the
+    oracle's to 1e-5 of scale, and the MAPE to 1e-4."""
+    name, mk, ipt, t, theta, tpw, level = case
+    say("iact fp64 distances", name)
+    x = mk()
+    n = x.shape[1]
+    y, tr, cnt = run("iact", to_dev(x), 2, ipt, table_size=t, threshold=theta, tables_per_wave=tpw, level=level)
+    yv, sv = oracle.region_values_f32out(x)
+    ora = oracle.iact(x, yv, sv, ipt, t, theta, tables_per_wave=tpw, group=group_of(level, 256),
+                      out_init=np.full_like(yv, SENTINEL), dist_fp64=True, band=GATE_BAND)
+    gdec, f = trace_dec(tr)
+    gw = np.where(f["writer_valid"], f["writer"], -1)
+    gcode = np.where(gdec >= 0, gdec.astype(np.int32) * 128 + gw + 1, -1)
+    ocode = np.where(ora["dec"] >= 0, ora["dec"].astype(np.int32) * 128 + ora["writer"] + 1, -1)
+    agree, compared, explained, cascaded = compare_decisions(gcode, ocode, ipt, ora["fragile"], lag=0)
+    assert agree >= 0.9999 * compared
+    if name == "flip":
+        assert explained == 1  # the constructed wave parts at its fragile step
+    say("  decisions agree %d/%d, explained %d, fragile records %d" % (agree, compared, explained,
+                                                                       int(ora["fragile"].sum())))
+    same_wave = np.all(gcode.reshape(-1, ipt) == ocode.reshape(-1, ipt), axis=1)
+    L = oracle.num_lanes(n, ipt)
+    i = np.arange(n)
+    rec = ((i % L) // 64) * ipt + i // L
+    mask = same_wave[(i % L) // 64] & ~ora["fragile"].astype(bool)[rec]
+    check_outputs(y, ora["out"], ora["scale"], mask=mask, what="iact fp64 " + name)
+    if mask.any():
+        ref, _ = exact_ref(x)
+        mg, mo = mape_pair(ref, y, ora["out"], mask=mask)
+        assert abs(mg - mo) <= 1e-4
+
+
 # --------------------------------------------------------------------- TAF
 
 TAF_CASES = [
@@ -157,11 +217,27 @@ TAF_CASES = [
 ]
 
 
+# Decision gate: a mismatch is explained only by a statistic within 1e-5
+# relative of its threshold (with the engine fed the GPU's own FP32 region
+# values, both sides compute every statistic from identical numbers).
+GATE_BAND = 1e-5
+
+
 def taf_band(theta):
-    """Relative band around the threshold inside which the GPU's FP32
-    region outputs (a few ulp from the FP64 values) may move a lane's RSD
-    across it: |dRSD| <~ 2 eps (1 + RSD) with eps <= 2e-6."""
+    """Relative band for the free-running comparison, where the oracle's
+    region values are the FP64 prices rounded to FP32 and the GPU's are its
+    own FP32 evaluations, a few ulp apart: such a difference moves a lane's
+    RSD by up to about 2 eps (1 + RSD) with eps <= 2e-6.  Used only to
+    decide which waves' outputs can be compared; decisions are gated by the
+    replay at GATE_BAND."""
     return 1e-5 + 4e-6 * (1.0 + theta) / theta
+
+
+def gpu_exact_values(x_dev):
+    """The uncounted exact kernel's FP32 outputs, as float64 (the value
+    source of the decision replay)."""
+    y, _, _ = run("exact", x_dev, 2, 1, trace=False, counters=False)
+    return y
 
 
 @pytest.mark.parametrize("case", TAF_CASES, ids=[c[0] for c in TAF_CASES])
@@ -182,9 +258,11 @@ def test_taf_block_sizes_match_oracle(level, block):
 
 def check_taf(name, x, ipt, h, p, theta, level, block):
     n = x.shape[1]
-    y, tr, cnt = run("taf", to_dev(x), 2, ipt, block_size=block, history_size=h, prediction_size=p,
+    xd = to_dev(x)
+    y, tr, cnt = run("taf", xd, 2, ipt, block_size=block, history_size=h, prediction_size=p,
                      rsd_threshold=theta, level=level)
     yv, sv = oracle.region_values_f32out(x)
+    replay_taf(name, y, tr, gpu_exact_values(xd), sv, ipt, h, p, theta, level, block)
     ora = oracle.taf(yv, sv, ipt, h, p, theta, band=taf_band(theta), group=group_of(level, block),
                      out_init=np.full_like(yv, SENTINEL))
     gdec, f = trace_dec(tr)
@@ -217,6 +295,31 @@ def check_taf(name, x, ipt, h, p, theta, level, block):
     assert abs(mg - mo) <= 1e-4
     assert cnt[0] == n
     say("  approx lanes %.4f  mape gpu %.3g oracle %.3g" % (cnt[1] / n, mg, mo))
+
+
+def replay_taf(name, y, tr, y_exact_gpu, sv, ipt, h, p, theta, level, block):
+    """Decision replay: the oracle's TAF engine runs on the GPU exact
+    kernel's FP32 outputs, so its RSD statistics come from the very numbers
+    the kernel's windows hold.  Every (wave, step) decision must agree
+    except where the oracle marks a statistic within GATE_BAND relative of
+    the threshold that could flip the vote (the rest of that wave is then
+    not compared); at least 99.99% agree; and on the agreeing waves the
+    outputs are bit for bit the oracle's (both reuse identical values)."""
+    ora = oracle.taf(y_exact_gpu, sv, ipt, h, p, theta, band=GATE_BAND, group=group_of(level, block),
+                     out_init=np.full_like(y_exact_gpu, SENTINEL))
+    gdec, f = trace_dec(tr)
+    odec = ora["dec"]
+    if level == "thread":
+        gdec = np.where(f["active"], f["napprox"], -1)
+        odec = np.where(ora["dec"] >= 0, ora["napprox"], -1)
+    agree, compared, explained, cascaded = compare_decisions(gdec, odec, ipt, ora["fragile"], lag=1)
+    assert agree >= 0.9999 * compared
+    say("  replay: decisions agree %d/%d, explained %d" % (agree, compared, explained))
+    n = y.shape[1]
+    same_wave = np.all(gdec.reshape(-1, ipt) == odec.reshape(-1, ipt), axis=1)
+    L = oracle.num_lanes(n, ipt)
+    mask = same_wave[(np.arange(n) % L) // 64]
+    assert np.array_equal(y[:, mask], ora["out"][:, mask]), "replayed outputs differ on agreeing waves"
 
 
 # ------------------------------------------------------------- perforation
@@ -360,7 +463,11 @@ def test_full_size_config_against_oracle():
     ref, scale = exact_ref(x)
     ye, _, c = run("exact", xd, 2, 1, trace=False)
     check_outputs(ye, ref, scale, what="exact 2^24")
-    del ye
+    # the uncounted launch the benchmark times (one item per lane), every element
+    yu, _, _ = run("exact", xd, 2, 1, trace=False, counters=False)
+    check_outputs(yu, ref, scale, what="uncounted exact 2^24")
+    assert np.array_equal(yu, ye)
+    del ye, yu
     yv, sv = oracle.region_values_f32out(x)
     say("full-size iact")
     yi, ti, _ = run("iact", xd, 2, 16, table_size=8, threshold=0.05)
@@ -370,6 +477,7 @@ def test_full_size_config_against_oracle():
     del yi, ora
     say("full-size taf")
     yt, tt, _ = run("taf", xd, 2, 16, history_size=4, prediction_size=4, rsd_threshold=0.01)
+    replay_taf("2^24", yt, tt, gpu_exact_values(xd), sv, 16, 4, 4, 0.01, "wave", 256)
     ora = oracle.taf(yv, sv, 16, 4, 4, 0.01, band=taf_band(0.01))
     compare_decisions(trace_dec(tt)[0], ora["dec"], 16, ora["fragile"], lag=1)
     mg, mo = mape_pair(ref, yt, ora["out"])

@@ -272,3 +272,180 @@ def test_mape_hand_example():
 def test_mape_of_exact_is_zero():
     x = np.linspace(-3, 3, 101)
     assert oracle.mape(x, x) == (0.0, int((np.abs(x) < oracle.MAPE_TAU).sum()), 0.0)
+
+
+# ------------------------------------------------- iACT distance precision
+
+def _real_case(data, max_n=300):
+    """Real-valued inputs (not on a grid): FP32 and FP64 distances differ in
+    their last bits, so the two readings can choose differently near ties."""
+    n = data.draw(st.integers(1, max_n))
+    ipt = data.draw(st.integers(1, 6))
+    seed = data.draw(st.integers(0, 2**31 - 1))
+    g = np.random.default_rng(seed)
+    x = g.integers(0, 4, (2, n)).astype(np.float64) + g.normal(0, 0.3, (2, n))
+    return n, ipt, x.astype(np.float32).astype(np.float64)
+
+
+@settings(max_examples=150, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(data=st.data())
+def test_iact_fp64_distances_match_brute_force(data):
+    """The FP64 reading is the plain definition: on real-valued inputs it
+    takes every decision the brute-force re-statement (distances in Python's
+    double precision, summed in the same order) takes."""
+    n, ipt, x = _real_case(data)
+    tsize = data.draw(st.integers(1, 4))
+    theta = data.draw(st.sampled_from([0.0, 0.5, 1.5, 2.5]))
+    tpw = data.draw(st.sampled_from([1, 2, 4]))
+    group = data.draw(st.sampled_from([1, 64, 128]))
+    y = np.stack([x[0] * 10 + x[1], x[1] - x[0]])
+    r = oracle.iact(x, y, None, ipt, tsize, theta, tables_per_wave=tpw, group=group, dist_fp64=True)
+    xs = [tuple(float(np.float32(v)) for v in x[:, i]) for i in range(n)]
+    ys = [tuple(y[:, i]) for i in range(n)]
+    bout, bdec = brute.iact(xs, ys, ipt, tsize, float(np.float32(theta)), tpw, group)
+    assert np.array_equal(r["out"].T, np.array(bout))
+    for (w, k), d in bdec.items():
+        assert r["dec"][w * ipt + k] == d, (w, k)
+
+
+@settings(max_examples=100, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(data=st.data())
+def test_iact_fp32_and_fp64_readings_agree_on_a_grid(data):
+    """On integer-grid inputs every squared distance is exact in FP32, so
+    the FP32 reading (the precision the kernels decide in) and the FP64
+    definition take identical decisions, writers and outputs."""
+    n, ipt, x = _grid_case(data)
+    tsize = data.draw(st.integers(1, 4))
+    theta = data.draw(st.sampled_from([0.5, 1.5, 2.5]))
+    y = np.stack([x[0] * 10 + x[1], x[1] - x[0]])
+    a = oracle.iact(x, y, None, ipt, tsize, theta)
+    b = oracle.iact(x, y, None, ipt, tsize, theta, dist_fp64=True)
+    for key in ("out", "dec", "votes", "writer", "napprox"):
+        assert np.array_equal(a[key], b[key]), key
+
+
+def test_iact_precision_mismatches_are_all_marked_fragile():
+    """Real inputs whose distances cluster at the threshold: the FP32
+    reading and the FP64 definition disagree somewhere, and the first
+    disagreement of every wave (decision or writer) falls on a (wave, step)
+    that the FP64 run marks fragile at a band of 1e-5; the band is what
+    explains a GPU/oracle disagreement in the GPU parity tests."""
+    from paper_2308_16877_amd import inputs
+    x = inputs.periodic(65536, 8, jitter=1e-3)
+    y, s = oracle.region_values_f32out(x)
+    # a threshold at the median nearest-pool-tuple distance puts many lanes at it
+    a = oracle.iact(x, y, s, 16, 8, 0.08)
+    b = oracle.iact(x, y, s, 16, 8, 0.08, dist_fp64=True, band=1e-5)
+    code_a = np.where(a["dec"] >= 0, a["dec"].astype(np.int32) * 128 + a["writer"] + 1, -1).reshape(-1, 16)
+    code_b = np.where(b["dec"] >= 0, b["dec"].astype(np.int32) * 128 + b["writer"] + 1, -1).reshape(-1, 16)
+    fr = b["fragile"].reshape(-1, 16)
+    neq = code_a != code_b
+    waves = np.nonzero(neq.any(axis=1))[0]
+    for w in waves:
+        k = int(np.argmax(neq[w]))
+        assert fr[w, k], (w, k)
+    assert fr.sum() >= len(waves)
+    print("waves where the readings part: %d of %d; fragile steps %d" % (len(waves), fr.shape[0], int(fr.sum())))
+    # and outside the waves where the readings part, the outputs agree
+    # except at steps whose arg-min was a near tie
+    L = oracle.num_lanes(65536, 16)
+    i = np.arange(65536)
+    wave, step = (i % L) // 64, i // L
+    keep = ~neq.any(axis=1)[wave] & ~fr.astype(bool)[wave, step]
+    assert np.array_equal(a["out"][:, keep], b["out"][:, keep])
+
+
+def test_iact_precision_flip_is_marked_fragile():
+    """A wave built so that the readings disagree: every lane stores (10, 10)
+    at step 0 and meets (10.4447126, 10.7893143) at step 1, at a distance
+    within 4e-7 of theta = 0.9059726 -- below it in FP64, not below it in
+    FP32 (the FP32 sum rounds up).  The FP64 run approximates step 1, the
+    FP32 run computes it, and the FP64 run marks that step fragile."""
+    th = 0.9059725999832153
+    x = np.zeros((2, 128), np.float32)
+    x[:, :64] = 10.0
+    x[0, 64:], x[1, 64:] = 10.44471263885498, 10.789314270019531
+    x = x.astype(np.float64)
+    y = np.stack([x[0] + 1.0, x[1] + 2.0])
+    a = oracle.iact(x, y, None, 2, 2, th)
+    b = oracle.iact(x, y, None, 2, 2, th, dist_fp64=True, band=1e-5)
+    assert a["dec"][1] == 0 and b["dec"][1] == 1
+    assert b["fragile"][1] == 1 and b["fragile"][0] == 0
+
+
+def test_iact_fragile_band_marks_a_threshold_tie():
+    """One wave of identical inputs at distance exactly theta from the
+    stored entry: every lane's statistic is at the threshold, the vote is
+    marked fragile at any positive band, and with band 0 nothing is."""
+    x = np.zeros((2, 128))
+    x[0, 64:] = 1.5  # step 1: distance 1.5 from step 0's inputs
+    y = np.stack([x[0] + 1.0, x[1] + 2.0])
+    r = oracle.iact(x, y, None, 2, 2, 1.5, dist_fp64=True, band=1e-5)
+    assert r["fragile"][1] == 1 and r["fragile"][0] == 0
+    assert r["dec"][1] == 0  # strict <: a distance equal to theta does not qualify
+    r0 = oracle.iact(x, y, None, 2, 2, 1.5, dist_fp64=True)
+    assert not r0["fragile"].any()
+
+
+# ------------------------------------------------------------------- Adam
+
+def test_adam_first_step_is_the_normalised_gradient():
+    """From zero moments the bias corrections make m_hat = g and v_hat = g^2
+    at step 1, so each parameter moves by -lr g / (|g| + eps): almost
+    exactly lr against the sign of its gradient (eps = 0.5 makes a
+    misplaced eps, e.g. under the square root, visible)."""
+    g = np.random.default_rng(3).standard_normal((3, 50))
+    w0 = np.random.default_rng(4).standard_normal(50)
+    z = np.zeros(50)
+    gs = g.sum(0)
+    for eps in (1e-8, 0.5):
+        w, m, v = oracle.adam(g, w0, z, z, 0.1, 0.9, 0.999, eps, 1)
+        assert np.allclose(w, w0 - 0.1 * gs / (np.abs(gs) + eps), rtol=0, atol=1e-14)
+        assert np.allclose(m, 0.1 * gs, rtol=1e-14) and np.allclose(v, 0.001 * gs * gs, rtol=1e-12)
+
+
+def test_adam_constant_gradient_moves_a_fixed_amount_per_step():
+    """With a constant gradient g from zero moments, m_t = (1 - b1^t) g and
+    v_t = (1 - b2^t) g^2, so every step moves the parameter by exactly
+    -lr g / (|g| + eps) whatever t (a wrong power in a bias correction
+    breaks this from the second step on)."""
+    g = np.array([[0.3, -2.0, 1e-3, 7.0]])
+    w = np.zeros(4)
+    m = np.zeros(4)
+    v = np.zeros(4)
+    for t in range(1, 9):
+        w, m, v = oracle.adam(g, w, m, v, 0.01, 0.9, 0.99, 1e-3, t)
+        assert np.allclose(w, -t * 0.01 * g[0] / (np.abs(g[0]) + 1e-3), rtol=1e-12, atol=0)
+
+
+def test_adam_alternating_gradient_follows_the_geometric_series():
+    """g_t = (-1)^(t+1) c: v_hat = c^2 at every t, while the first moment is
+    a geometric series of ratio -b1, m_t = (1 - b1) g_t (1 - (-b1)^t) / (1 + b1)
+    -- which tells b1 from b2, and m from v."""
+    c = np.array([0.5, -1.5, 3.0])
+    b1, b2, lr, eps = 0.8, 0.95, 0.05, 0.0
+    w = np.zeros(3)
+    m = np.zeros(3)
+    v = np.zeros(3)
+    for t in range(1, 7):
+        g = c * (-1) ** (t + 1)
+        w_prev = w
+        w, m, v = oracle.adam(g[None, :], w, m, v, lr, b1, b2, eps, t)
+        m_closed = (1 - b1) * g * (1 - (-b1) ** t) / (1 + b1)
+        assert np.allclose(m, m_closed, rtol=1e-13)
+        step = lr * (m_closed / (1 - b1 ** t)) / np.abs(c)
+        assert np.allclose(w_prev - w, step, rtol=1e-12)
+
+
+def test_adam_sums_the_partial_gradients():
+    """The gradient is the sum of the partials: any split of it into blocks
+    gives the one-block step (to rounding)."""
+    rng = np.random.default_rng(5)
+    total = rng.standard_normal(40)
+    parts = rng.standard_normal((5, 40))
+    parts[-1] = total - parts[:-1].sum(0)
+    w0, m0, v0 = rng.standard_normal(40), rng.standard_normal(40) * 0.1, rng.random(40) * 0.1
+    a = oracle.adam(parts, w0, m0, v0, 1e-2, 0.9, 0.999, 1e-8, 3)
+    b = oracle.adam(total[None, :], w0, m0, v0, 1e-2, 0.9, 0.999, 1e-8, 3)
+    for u, w in zip(a, b):
+        assert np.allclose(u, w, rtol=1e-12, atol=1e-15)
