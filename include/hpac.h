@@ -46,6 +46,7 @@ typedef int32_t hpac_status;
 #define HPAC_EINVAL (-1)       /* an argument is out of range or NULL       */
 #define HPAC_EUNSUPPORTED (-2) /* valid request the library does not provide */
 #define HPAC_EHIP (-3)         /* the HIP runtime reported an error         */
+#define HPAC_ENUMERIC (-4)     /* the computation left its numeric domain   */
 
 /* Regions.  Inputs and outputs are structure-of-arrays columns of n
  * elements (the column-major, stride-n array sections of section 3.2).
@@ -304,7 +305,18 @@ typedef struct hpac_hydro_state {
   int32_t *rho_hg, *z_hg;
   double *clock;                /* [0] time, [1] last time step */
   double *dt_partials;          /* hpac_hydro_partials(n) doubles */
+  int32_t *status;              /* numeric-failure flags, HPAC_HYDRO_BAD_* (one int32) */
 } hpac_hydro_state;
+
+/* Numeric-failure flags, OR-ed into *state->status by the step kernels
+ * (zeroed by hpac_hydro_init) when an element's volume is not positive
+ * (a tangled mesh: too large a Courant factor or time step) or the step's
+ * time step is not finite and positive.  The step carries on (no index
+ * depends on the values, so a failed run cannot fault); the caller learns
+ * of the failure at its next read of the flags: hpac_hydro_check, or a
+ * copy of *status after the stream has passed the step. */
+#define HPAC_HYDRO_BAD_VOLUME 1
+#define HPAC_HYDRO_BAD_DT 2
 
 typedef struct hpac_hydro_tech {
   int32_t eos_history, eos_prediction; /* EOS TAF; history 0 = exact */
@@ -348,6 +360,11 @@ hpac_status hpac_hydro_step(const hpac_hydro_params *params, const hpac_hydro_te
  * `steps` is odd and in state->u if it is even. */
 hpac_status hpac_hydro_run(const hpac_hydro_params *params, const hpac_hydro_tech *tech, int32_t first_step,
                            int32_t steps, const hpac_hydro_state *state, void *stream);
+
+/* Waits for `stream`, then reads *state->status: HPAC_OK if no flag is set,
+ * HPAC_ENUMERIC (the message names the flags) otherwise.  The one hydro call
+ * that waits for the device. */
+hpac_status hpac_hydro_check(const hpac_hydro_state *state, void *stream);
 
 /* ------------------------------------------------------------------------
  * Binomial Options.  One wavefront prices one option on an N-step
@@ -407,7 +424,7 @@ hpac_status hpac_probe_valu(float *out, int32_t workgroups, int32_t iters, int32
 /* Thread-local message describing the last non-OK status; never NULL. */
 const char *hpac_last_error(void);
 
-/* ABI version of this header: 1. */
+/* ABI version of this header: 2 (the hydro state gained `status`). */
 int32_t hpac_abi_version(void);
 
 #ifdef __cplusplus

@@ -356,6 +356,7 @@ class HydroState:
         self.rho_eos, self.z_eos, self.rho_hg, self.z_hg = (np.zeros(E, np.int32) for _ in range(4))
         self.clock = z(2)
         self.eos_h, self.hg_h = eos_h, hg_h
+        self.flags = 0  # numeric-failure flags of the steps taken (see hydro_step)
 
     def _cpar(self):
         return _HyPar(n=self.n, **self.par)
@@ -425,8 +426,11 @@ def hydro_step(s, step, eos=None, hg=None, perfo=None, band=0.0, record=False):
     cp, cs = s._cpar(), s._cstate()
     rc = _load().hy_step(ctypes.byref(cp), ctypes.byref(t), int(step), ctypes.byref(cs),
                          ctypes.byref(rec) if rec is not None else None)
-    if rc != 0:
+    if rc < 0:
         raise ValueError("hy_step rejected its arguments")
+    # numeric-failure flags (1: a non-positive element volume, 2: a time step
+    # that is not finite and positive), accumulated over the steps taken
+    s.flags |= rc
     return out
 
 

@@ -344,8 +344,9 @@ static double hy_force_elem(const hy_par *P, hy_state *S, int64_t z, int hg) {
   return bound;
 }
 
-/* EOS region for one element (accurate path); y = (e, p, q, c). */
-static void hy_eos_elem(const hy_par *P, const hy_state *S, int64_t z, double dt, double y[4]) {
+/* EOS region for one element (accurate path); y = (e, p, q, c).  Returns
+ * the element's new volume. */
+static double hy_eos_elem(const hy_par *P, const hy_state *S, int64_t z, double dt, double y[4]) {
   const int64_t E = hy_elems(P);
   double xc[8][3], u0[8][3], u1[8][3];
   hy_gather(P, S, z, xc, u0, S->u);
@@ -368,9 +369,16 @@ static void hy_eos_elem(const hy_par *P, const hy_state *S, int64_t z, double dt
   y[1] = p1;
   y[2] = q1;
   y[3] = sqrt(P->gamma * fmax(p1, 0.0) / rho1);
+  return V1;
 }
 
-/* One timestep.  step = the timestep index (the perforation offset). */
+/* One timestep.  step = the timestep index (the perforation offset).
+ * Returns -1 for invalid arguments, else the step's numeric-failure flags:
+ * 0, or HY_BAD_VOLUME if an element volume (after the force or the EOS
+ * phase) was not positive, plus HY_BAD_DT if the time step was not finite
+ * and positive.  The step is completed either way. */
+#define HY_BAD_VOLUME 1
+#define HY_BAD_DT 2
 int hy_step(const hy_par *P, const hy_tech *T, int32_t step, hy_state *S, hy_rec *R) {
   const int64_t n = P->n, m = n + 1, E = hy_elems(P), Nn = hy_nodes(P);
   if ((T->eos_h && (T->eos_h > HY_MAX_H || T->eos_p < 1)) || (T->hg_h && (T->hg_h > HY_MAX_H || T->hg_p < 1)))
@@ -397,23 +405,28 @@ int hy_step(const hy_par *P, const hy_tech *T, int32_t step, hy_state *S, hy_rec
   /* 1. forces (hourglass region under TAF, perforation or exact) and the
    * time-step bound of every element */
   double dtmin = INFINITY;
+  int bad = 0;
   if (T->perfo_param) {
     const int64_t L = HY_WAVE * (((E + T->perfo_ipt - 1) / T->perfo_ipt + HY_WAVE - 1) / HY_WAVE);
-#pragma omp parallel for schedule(static) reduction(min : dtmin)
+#pragma omp parallel for schedule(static) reduction(min : dtmin) reduction(| : bad)
     for (int64_t l = 0; l < L; ++l)
       for (int32_t k = 0; k < T->perfo_ipt; ++k) {
         const int64_t z = l + (int64_t)k * L;
         if (z >= E) continue;
         const double b = hy_force_elem(P, S, z, hy_perfo_skip(T, z, E, k, step) ? HY_HG_NONE : HY_HG_COMPUTE);
         dtmin = fmin(dtmin, b);
+        if (!(S->vol[z] > 0.0)) bad |= HY_BAD_VOLUME;
       }
   } else {
-#pragma omp parallel for schedule(static) reduction(min : dtmin)
+#pragma omp parallel for schedule(static) reduction(min : dtmin) reduction(| : bad)
     for (int64_t g = 0; g < NGH; ++g) {
       const int64_t z0 = g * GH, z1 = z0 + GH < E ? z0 + GH : E;
       const int act = (int)(z1 - z0);
       if (T->hg_h && S->rho_hg[g] > 0) {
-        for (int64_t z = z0; z < z1; ++z) dtmin = fmin(dtmin, hy_force_elem(P, S, z, HY_HG_REUSE));
+        for (int64_t z = z0; z < z1; ++z) {
+          dtmin = fmin(dtmin, hy_force_elem(P, S, z, HY_HG_REUSE));
+          if (!(S->vol[z] > 0.0)) bad |= HY_BAD_VOLUME;
+        }
         S->rho_hg[g]--;
         if (R && R->dec_hg) R->dec_hg[g] = 1;
         continue;
@@ -421,6 +434,7 @@ int hy_step(const hy_par *P, const hy_tech *T, int32_t step, hy_state *S, hy_rec
       int yes = 0, voted = 0, near_yes = 0, near_no = 0;
       for (int64_t z = z0; z < z1; ++z) {
         dtmin = fmin(dtmin, hy_force_elem(P, S, z, HY_HG_COMPUTE));
+        if (!(S->vol[z] > 0.0)) bad |= HY_BAD_VOLUME;
         if (!T->hg_h) continue;
         double y[24];
         for (int o = 0; o < 24; ++o) y[o] = S->fhg[o * E + z];
@@ -443,6 +457,7 @@ int hy_step(const hy_par *P, const hy_tech *T, int32_t step, hy_state *S, hy_rec
 
   /* 2. time step */
   const double dt = fmin(dtmin, P->growth * S->clock[1]);
+  if (!(dt > 0.0) || !isfinite(dt)) bad |= HY_BAD_DT;
 
   /* 3. nodes: gather corner forces, momentum, boundary conditions, positions */
 #pragma omp parallel for schedule(static)
@@ -465,7 +480,7 @@ int hy_step(const hy_par *P, const hy_tech *T, int32_t step, hy_state *S, hy_rec
   }
 
   /* 4. EOS region per element (TAF or exact) */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) reduction(| : bad)
   for (int64_t g = 0; g < NGE; ++g) {
     const int64_t z0 = g * GE, z1 = z0 + GE < E ? z0 + GE : E;
     const int act = (int)(z1 - z0);
@@ -477,7 +492,7 @@ int hy_step(const hy_par *P, const hy_tech *T, int32_t step, hy_state *S, hy_rec
     int yes = 0, voted = 0, near_yes = 0, near_no = 0;
     for (int64_t z = z0; z < z1; ++z) {
       double y[4];
-      hy_eos_elem(P, S, z, dt, y);
+      if (!(hy_eos_elem(P, S, z, dt, y) > 0.0)) bad |= HY_BAD_VOLUME;
       S->e[z] = y[0];
       S->p[z] = y[1];
       S->q[z] = y[2];
@@ -505,7 +520,7 @@ int hy_step(const hy_par *P, const hy_tech *T, int32_t step, hy_state *S, hy_rec
     for (int d = 0; d < 3; ++d) S->u[d][v] = S->unew[d][v];
   S->clock[0] += dt;
   S->clock[1] = dt;
-  return 0;
+  return bad;
 }
 
 /* Internal and kinetic energy of the state. */

@@ -12,6 +12,9 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+static_assert(hpac::kHydroBadVolume == HPAC_HYDRO_BAD_VOLUME && hpac::kHydroBadDt == HPAC_HYDRO_BAD_DT,
+              "hydro flag bits");
+
 namespace {
 
 thread_local char g_err[512] = "no error";
@@ -160,7 +163,7 @@ hpac_status hip_status(const char *fn, hipError_t e) {
 
 extern "C" {
 
-int32_t hpac_abi_version(void) { return 1; }
+int32_t hpac_abi_version(void) { return 2; }
 
 const char *hpac_last_error(void) { return g_err; }
 
@@ -462,6 +465,7 @@ static hpac_status check_hydro_state(const char *fn, const hpac_hydro_state *S) 
     if (!aligned4(x)) return fail(HPAC_EINVAL, "%s: a mesh field is NULL or misaligned", fn);
   if (!S->clock || (uintptr_t)S->clock % 8 || !S->dt_partials || (uintptr_t)S->dt_partials % 8)
     return fail(HPAC_EINVAL, "%s: clock or dt_partials is NULL or misaligned", fn);
+  if (!aligned4(S->status)) return fail(HPAC_EINVAL, "%s: status is NULL or misaligned", fn);
   return HPAC_OK;
 }
 
@@ -501,6 +505,7 @@ static hpac::HydroArgs hydro_args(const hpac_hydro_params *P, const hpac_hydro_s
   a.z_hg = S->z_hg;
   a.clock = S->clock;
   a.dt_partials = S->dt_partials;
+  a.status = S->status;
   a.hg_ipt = 1;
   a.hg_L = hpac::hydro_lanes(a.E, 1);
   return a;
@@ -636,6 +641,20 @@ hpac_status hpac_hydro_run(const hpac_hydro_params *params, const hpac_hydro_tec
       a.un[d] = t;
     }
   }
+  return HPAC_OK;
+}
+
+hpac_status hpac_hydro_check(const hpac_hydro_state *state, void *stream) {
+  const char *fn = "hpac_hydro_check";
+  if (!state || !aligned4(state->status)) return fail(HPAC_EINVAL, "%s: status is NULL or misaligned", fn);
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  int32_t flags = 0;
+  if (e == hipSuccess) e = hipMemcpy(&flags, state->status, sizeof flags, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_status(fn, e);
+  if (flags)
+    return fail(HPAC_ENUMERIC, "%s: the hydro left its numeric domain:%s%s", fn,
+                flags & HPAC_HYDRO_BAD_VOLUME ? " a non-positive element volume (tangled mesh)" : "",
+                flags & HPAC_HYDRO_BAD_DT ? " a time step that is not finite and positive" : "");
   return HPAC_OK;
 }
 

@@ -329,6 +329,7 @@ __global__ void __launch_bounds__(256) k_hydro_init_groups(HydroArgs a, double d
   if (g == 0) {
     a.clock[0] = 0.0;
     a.clock[1] = dt0;
+    *a.status = 0;
   }
   if (g >= a.E) return;
   if (a.rho_eos) a.rho_eos[g] = 0, a.z_eos[g] = 0;
@@ -401,6 +402,7 @@ __global__ void __launch_bounds__(256) k_hydro_force(HydroArgs a) {
       gather3(a.u, ei, n, u);
       const float V = hex_volume<true>(x, B);
       a.vol[z] = V;
+      if (!(V > 0.0f)) atomicOr(a.status, kHydroBadVolume);  // tangled (or NaN) element
       const float pq = a.p[z] + a.q[z];
       // volume rate sum B . u (B sums to zero, so relative to corner 0)
       float vdot = 0.0f;
@@ -497,6 +499,7 @@ __global__ void __launch_bounds__(256) k_hydro_dt(HydroArgs a, int64_t parts) {
   m = block_min(m, red);
   if (threadIdx.x == 0) {
     const double dt = fmin(m, a.growth * a.clock[1]);
+    if (!(dt > 0.0) || !isfinite(dt)) atomicOr(a.status, kHydroBadDt);
     a.clock[0] += dt;
     a.clock[1] = dt;
   }
@@ -596,6 +599,7 @@ __global__ void __launch_bounds__(256) k_hydro_eos(HydroArgs a) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) W = __builtin_fmaf(a.force[(c * 3 + d) * E + z], 0.5f * (u0[c][d] + u1[c][d]), W);
     const float V1 = hex_volume<true>(x, B);
+    if (!(V1 > 0.0f)) atomicOr(a.status, kHydroBadVolume);
     // volume rate sum B . u (B sums to zero, so relative to corner 0)
     float vdot = 0.0f;
 #pragma unroll

@@ -24,6 +24,7 @@ struct HydroArgs {
   float *whg;
   int32_t *rho_hg, *z_hg;
   double *clock, *dt_partials;
+  int32_t *status;        // numeric-failure flags (bits as hpac.h's HPAC_HYDRO_BAD_*)
   int8_t *dec_eos, *dec_hg;
   // technique of this step
   int eos_h, eos_p;
@@ -35,6 +36,7 @@ struct HydroArgs {
   int64_t hg_L;    // its logical lanes
   int32_t step;    // timestep index (perforation offset)
 };
+constexpr int32_t kHydroBadVolume = 1, kHydroBadDt = 2;
 int64_t hydro_lanes(int64_t E, int ipt);
 int64_t hydro_partials(int64_t E);
 hipError_t launch_hydro_init(const HydroArgs &a, double e_origin, double dt0, hipStream_t stream);

@@ -12,7 +12,8 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libhpac.so")
 
-HPAC_OK, HPAC_EINVAL, HPAC_EUNSUPPORTED, HPAC_EHIP = 0, -1, -2, -3
+HPAC_OK, HPAC_EINVAL, HPAC_EUNSUPPORTED, HPAC_EHIP, HPAC_ENUMERIC = 0, -1, -2, -3, -4
+HYDRO_BAD_VOLUME, HYDRO_BAD_DT = 1, 2
 REGION_BS_PRICE, REGION_BS_PRICE_GRAD, REGION_BS_PRICE_F16, REGION_BS_PRICE_BF16 = 0, 1, 2, 3
 REGION_BINOMIAL = 4
 REGION_SHAPE = {REGION_BS_PRICE: (5, 2), REGION_BS_PRICE_GRAD: (5, 12), REGION_BS_PRICE_F16: (5, 2),
@@ -70,7 +71,7 @@ class hpac_hydro_state(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p * 3), ("u", ctypes.c_void_p * 3), ("unew", ctypes.c_void_p * 3)] + \
                [(f, ctypes.c_void_p) for f in ("mnode", "e", "p", "q", "c", "vol", "mass", "force", "weos",
                                                 "rho_eos", "z_eos", "whg", "rho_hg", "z_hg", "clock",
-                                                "dt_partials")]
+                                                "dt_partials", "status")]
 
 
 class hpac_hydro_tech(ctypes.Structure):
@@ -129,6 +130,8 @@ def lib():
     L.hpac_hydro_step.restype = i32
     L.hpac_hydro_run.argtypes = [HP, HT, i32, i32, HS, vp]
     L.hpac_hydro_run.restype = i32
+    L.hpac_hydro_check.argtypes = [HS, vp]
+    L.hpac_hydro_check.restype = i32
     L.hpac_bo_units.argtypes = [i64, i32]
     L.hpac_bo_units.restype = i64
     L.hpac_bo_exact.argtypes = [IO, i32, i32]
@@ -457,6 +460,12 @@ def hpac_hydro_step(params, tech, step, state, dec_eos=None, dec_hg=None, stream
 def hpac_hydro_run(params, tech, first_step, steps, state, stream=None):
     _call("hpac_hydro_run", lib().hpac_hydro_run(ctypes.byref(params), ctypes.byref(tech), int(first_step),
                                                  int(steps), ctypes.byref(state), _torch_stream(stream)))
+
+
+def hpac_hydro_check(state, stream=None):
+    """Raises HpacError(HPAC_ENUMERIC) if a hydro step left the numeric
+    domain (waits for the stream)."""
+    _call("hpac_hydro_check", lib().hpac_hydro_check(ctypes.byref(state), _torch_stream(stream)))
 
 
 # ------------------------------------------------------------ binomial

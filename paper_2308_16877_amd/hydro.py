@@ -72,6 +72,7 @@ class Hydro:
         self.z_hg = torch.zeros(E, **i32) if t.hg else None
         self.clock = torch.zeros(2, dtype=torch.float64, device=device)
         self.dt_partials = torch.zeros(hpac.hpac_hydro_partials(self.n), dtype=torch.float64, device=device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
         self.dec_eos = torch.zeros(E, dtype=torch.int8, device=device)
         self.dec_hg = torch.zeros(E, dtype=torch.int8, device=device)
         self.params = hpac.hpac_hydro_params(n=self.n, **self.par)
@@ -86,7 +87,8 @@ class Hydro:
             s.x[d] = self.x[d].data_ptr()
             s.u[d] = self.u[d].data_ptr()
             s.unew[d] = self.unew[d].data_ptr()
-        for f in self.FIELDS + ("weos", "rho_eos", "z_eos", "whg", "rho_hg", "z_hg", "clock", "dt_partials"):
+        for f in self.FIELDS + ("weos", "rho_eos", "z_eos", "whg", "rho_hg", "z_hg", "clock", "dt_partials",
+                                "status"):
             t = getattr(self, f)
             setattr(s, f, t.data_ptr() if t is not None else None)
         self.state = s
@@ -110,6 +112,11 @@ class Hydro:
         if steps % 2:
             self._swap_velocities()
         self.steps += steps
+
+    def check(self, stream=None):
+        """Raises hpac.HpacError (HPAC_ENUMERIC) if a step so far left the
+        numeric domain (a non-positive element volume or time step)."""
+        hpac.hpac_hydro_check(self.state, stream)
 
     def time(self):
         return float(self.clock[0])

@@ -24,7 +24,7 @@ def test_library_exports_every_declared_symbol():
     lib = hpac.lib()
     for name in names:
         assert hasattr(lib, name), name
-    assert lib.hpac_abi_version() == 1
+    assert lib.hpac_abi_version() == 2
 
 
 def test_lane_mapping():
@@ -137,6 +137,7 @@ def hydro_state(**over):
         setattr(s, f, FAKE)
     s.clock = FAKE
     s.dt_partials = FAKE
+    s.status = FAKE
     for k, v in over.items():
         setattr(s, k, v)
     return s
@@ -186,6 +187,12 @@ def test_invalid_hydro_arguments_are_rejected():
     expect(E, hstep, P, T, 0, hydro_state(e=0))
     expect(E, hstep, P, T, 0, hydro_state(force=FAKE + 2))
     expect(E, hstep, P, T, 0, hydro_state(clock=FAKE + 4))
+    # the numeric-failure flags are required, by the steps and by the check
+    msg = expect(E, hstep, P, T, 0, hydro_state(status=0))
+    assert "status" in msg
+    expect(E, hstep, P, T, 0, hydro_state(status=FAKE + 2))
+    expect(E, hinit, P, 1.0, hydro_state(status=0))
+    expect(E, hpac.hpac_hydro_check, hydro_state(status=0), 0)
     for bad in (dict(eos_history=9, eos_prediction=1), dict(eos_history=2, eos_prediction=0),
                 dict(hg_history=-1), dict(eos_history=2, eos_prediction=2, eos_threshold=-0.1),
                 dict(eos_history=2, eos_prediction=2, eos_level=3),
@@ -299,3 +306,4 @@ def test_short_or_mistyped_buffers_are_rejected_by_the_binding():
         hpac.hpac_mlp_adam(FAKE, 1, FAKE, torch.zeros(100), FAKE, 1e-3, 0.9, 0.999, 1e-8, 1)
     with pytest.raises(ValueError, match="dst holds"):
         hpac.hpac_probe_copy(FAKE, torch.zeros(3, dtype=torch.float32), 16)
+

@@ -270,3 +270,37 @@ def test_library_loop_equals_single_steps(tech, k):
         if va is not None:
             assert np.array_equal(va, gb[f]), f
     assert a.steps == b.steps == k + 4
+
+
+def test_numeric_failure_is_reported():
+    """The failure path: the tangling configuration of the oracle's test
+    (Courant factor 3, volume-change limit lifted, time step allowed to
+    double) sets the device's numeric-failure flag, which hpac_hydro_check
+    turns into HPAC_ENUMERIC, within a few steps of where the FP64 oracle
+    first reports a non-positive volume on the same run; the workload's own
+    constants raise nothing over 150 steps.  Nothing faults: no index
+    depends on a value."""
+    n, par = 10, dict(cfl=3.0, dvmax=10.0, growth=2.0)
+    s = oracle.hydro_init(n, sedov_origin_energy(n), **par)
+    first_oracle = None
+    for k in range(60):
+        oracle.hydro_step(s, k)
+        if s.flags and first_oracle is None:
+            first_oracle = k
+    h = Hydro(n, **par)
+    first = None
+    for k in range(60):
+        h.step()
+        try:
+            h.check()
+        except hpac.HpacError as e:
+            assert e.status == hpac.HPAC_ENUMERIC and "volume" in str(e), str(e)
+            first = k
+            break
+    say("first flagged step: GPU %s, oracle %s" % (first, first_oracle))
+    assert first is not None and first_oracle is not None and abs(first - first_oracle) <= 5
+    assert int(h.status.item()) & hpac.HYDRO_BAD_VOLUME
+    ok = Hydro(n)
+    ok.run(150)
+    ok.check()
+    assert int(ok.status.item()) == 0

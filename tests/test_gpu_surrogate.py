@@ -78,11 +78,9 @@ def test_adam_step():
     w, m, v = (torch.from_numpy(a.copy()).to(DEV) for a in (w0, m0, v0))
     hpac.hpac_mlp_adam(torch.from_numpy(parts.ravel()).to(DEV), nb, w, m, v, 1e-3, 0.9, 0.999, 1e-8, 5)
     torch.cuda.synchronize()
-    g = parts.astype(np.float64).sum(0)
-    b1, b2 = float(np.float32(0.9)), float(np.float32(0.999))  # the FP32 hyper-parameters
-    mr = b1 * m0 + (1 - b1) * g
-    vr = b2 * v0 + (1 - b2) * g * g
-    wr = w0 - float(np.float32(1e-3)) * (mr / (1 - b1 ** 5)) / (np.sqrt(vr / (1 - b2 ** 5)) + float(np.float32(1e-8)))
+    # the oracle's FP64 Adam step at the FP32 hyper-parameters the kernel receives
+    f = lambda q: float(np.float32(q))
+    wr, mr, vr = oracle.adam(parts, w0, m0, v0, f(1e-3), f(0.9), f(0.999), f(1e-8), 5)
     assert np.allclose(m.cpu().numpy(), mr, rtol=1e-6, atol=1e-7)
     assert np.allclose(v.cpu().numpy(), vr, rtol=1e-6, atol=1e-9)
     assert np.allclose(w.cpu().numpy(), wr, rtol=1e-6, atol=1e-6)

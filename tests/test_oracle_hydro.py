@@ -314,3 +314,23 @@ def test_block_level_taf_decides_per_256_elements():
         t = r["dec_eos"][:(len(r["dec_eos"]) // 256) * 256].reshape(-1, 256)
         split += int(np.sum((t == 1).any(axis=1) & (t == 0).any(axis=1)))
     assert split > 0
+
+
+def test_numeric_failure_flags_of_a_tangling_run():
+    """The failure path: with the volume-change limit lifted (dvmax 10), a
+    Courant factor of 3 and a time step allowed to double every step, the
+    blast tangles the mesh within a few tens of steps and the oracle
+    reports a non-positive element volume; with the workload's own
+    constants (Courant factor 0.3, dvmax 0.1) no step is flagged."""
+    n = 10
+    s = oracle.hydro_init(n, (1.0 / 8) * n ** 3, cfl=3.0, dvmax=10.0, growth=2.0)
+    first = None
+    for k in range(60):
+        oracle.hydro_step(s, k)
+        if s.flags and first is None:
+            first = k
+    assert s.flags & 1 and first is not None and first < 40
+    ok = oracle.hydro_init(n, (1.0 / 8) * n ** 3)
+    for k in range(150):
+        oracle.hydro_step(ok, k)
+    assert ok.flags == 0
