@@ -292,8 +292,10 @@ def time_pairs(torch, legs, steps, warmup):
 
 def greeks_leg(torch, hpac, x_dev, n, steps):
     """Call Greeks (upstream (1, 0)) for 2^24 options: exact forward + the
-    recomputing adjoint, against iACT (table 16, threshold 0.05) on the
-    price-and-Jacobian region + the saved-Jacobian VJP; on the benchmark's
+    recomputing adjoint, against iACT (table 16, threshold 0.05) memoizing
+    (price, gradient) by reference (the price-and-source region + the
+    backward recomputing at each source item) and by value (the
+    price-and-Jacobian region + the saved-Jacobian VJP); on the benchmark's
     options and on the wave-periodic variant, where iACT finds reuse."""
     from paper_2308_16877_amd import inputs
     res = greeks_point(torch, hpac, x_dev, n, steps)
@@ -309,29 +311,37 @@ def greeks_point(torch, hpac, x_dev, n, steps):
     ones = torch.ones(n, **f32)
     price = [torch.zeros(n, **f32) for _ in range(2)]
     grads_exact = [torch.zeros(n, **f32) for _ in range(5)]
-    grads_iact = [torch.zeros(n, **f32) for _ in range(5)]
+    grads_ref = [torch.zeros(n, **f32) for _ in range(5)]
+    grads_jac = [torch.zeros(n, **f32) for _ in range(5)]
     full = [torch.zeros(n, **f32) for _ in range(12)]
+    ref_out = [torch.zeros(n, **f32) for _ in range(2)] + [torch.zeros(n, dtype=torch.int32, device=dev)]
     stream = torch.cuda.current_stream()
     fwd_exact = hpac.prepare("exact", x_dev, price, items_per_lane=1, block_size=256, stream=stream)
-    fwd_iact = hpac.prepare("iact", x_dev, full, items_per_lane=16, block_size=256, stream=stream,
-                            region=hpac.REGION_BS_PRICE_GRAD, table_size=16, threshold=0.05)
+    fwd_ref = hpac.prepare("iact", x_dev, ref_out, items_per_lane=16, block_size=256, stream=stream,
+                           region=hpac.REGION_BS_PRICE_REF, table_size=16, threshold=0.05)
+    fwd_jac = hpac.prepare("iact", x_dev, full, items_per_lane=16, block_size=256, stream=stream,
+                           region=hpac.REGION_BS_PRICE_GRAD, table_size=16, threshold=0.05)
     legs = {
         "exact_fwd_adjoint": [fwd_exact, lambda: hpac.hpac_bs_adjoint(x_dev, ones, None, grads_exact)],
-        "iact_fwd_vjp": [fwd_iact, lambda: hpac.hpac_bs_vjp(full[2:], ones, None, grads_iact)],
+        "iact_ref_fwd_vjp": [fwd_ref, lambda: hpac.hpac_bs_vjp_ref(x_dev, ref_out[2], ones, None, grads_ref)],
+        "iact_jacobian_fwd_vjp": [fwd_jac, lambda: hpac.hpac_bs_vjp(full[2:], ones, None, grads_jac)],
     }
     t = time_pairs(torch, legs, steps, 2)
     cnt = torch.zeros(hpac.NUM_COUNTERS, dtype=torch.int64, device=dev)
-    hpac.hpac_iact(x_dev, full, 16, 0.05, items_per_lane=16, region=hpac.REGION_BS_PRICE_GRAD, counters=cnt)
-    hpac.hpac_bs_vjp(full[2:], ones, None, grads_iact)
+    hpac.hpac_iact(x_dev, ref_out, 16, 0.05, items_per_lane=16, region=hpac.REGION_BS_PRICE_REF, counters=cnt)
+    hpac.hpac_bs_vjp_ref(x_dev, ref_out[2], ones, None, grads_ref)
     torch.cuda.synchronize()
     c = cnt.cpu().tolist()
     return {"workload": "call Greeks (delta, dC/dK, theta, rho, vega) of the benchmark's 2^24 options",
-            "exact_fwd_adjoint_ms": t["exact_fwd_adjoint"], "iact_fwd_vjp_ms": t["iact_fwd_vjp"],
+            "exact_fwd_adjoint_ms": t["exact_fwd_adjoint"], "iact_fwd_vjp_ms": t["iact_ref_fwd_vjp"],
+            "iact_jacobian_fwd_vjp_ms": t["iact_jacobian_fwd_vjp"],
             "exact_items_per_s": n / (t["exact_fwd_adjoint"] * 1e-3),
-            "iact_items_per_s": n / (t["iact_fwd_vjp"] * 1e-3),
-            "iact_speedup_vs_exact": t["exact_fwd_adjoint"] / t["iact_fwd_vjp"],
+            "iact_items_per_s": n / (t["iact_ref_fwd_vjp"] * 1e-3),
+            "iact_speedup_vs_exact": t["exact_fwd_adjoint"] / t["iact_ref_fwd_vjp"],
+            "iact_jacobian_speedup_vs_exact": t["exact_fwd_adjoint"] / t["iact_jacobian_fwd_vjp"],
             "iact_approx_frac": c[1] / max(c[0], 1),
-            "iact_gradient_mape_vs_exact": mape_torch(torch, grads_exact, grads_iact)}
+            "iact_gradient_mape_vs_exact": mape_torch(torch, grads_exact, grads_ref),
+            "memo_forms_bitwise_equal": all(bool(torch.equal(a, b)) for a, b in zip(grads_ref, grads_jac))}
 
 
 def precision_leg(torch, hpac, x_dev, n, steps):

@@ -61,6 +61,15 @@ typedef int32_t hpac_status;
  *   columns, so a reused entry also reuses its gradients. */
 #define HPAC_REGION_BS_PRICE 0
 #define HPAC_REGION_BS_PRICE_GRAD 1
+/* HPAC_REGION_BS_PRICE_REF: the prices plus the item that produced them.
+ *   in (5): as above.  out (3): call, put (FP32), then an int32 column: the
+ *   item's own index where the region was evaluated, the source item of the
+ *   reused entry where iACT approximated (its inputs were stored with the
+ *   entry).  hpac_bs_vjp_ref recomputes the derivatives at the source item,
+ *   which reuses the memoized gradient by reference (4 bytes per item instead
+ *   of ten Jacobian columns).  Taken by hpac_exact and hpac_iact only (other
+ *   techniques return HPAC_EUNSUPPORTED); n <= 2^31 - 1. */
+#define HPAC_REGION_BS_PRICE_REF 5
 /* Reduced-precision bodies of HPAC_REGION_BS_PRICE (same inputs and outputs):
  *   _F16  every operation in FP16;
  *   _BF16 every operation at BF16 precision (inputs and each result rounded
@@ -196,6 +205,14 @@ hpac_status hpac_bs_vjp(int64_t n, const void *const *jacobian, const float *gra
                         void *const *grad_in, void *stream);
 hpac_status hpac_bs_adjoint(int64_t n, const void *const *in, const float *grad_call, const float *grad_put,
                             void *const *grad_in, void *stream);
+/* The same contraction for a forward on HPAC_REGION_BS_PRICE_REF: item i
+ * takes the derivatives of item source[i] (device int32 column of n),
+ * recomputed from in[5] at that item; equal bit for bit to hpac_bs_vjp of
+ * the Jacobian HPAC_REGION_BS_PRICE_GRAD would have saved under the same
+ * technique.  An index outside [0, n) yields NaN gradients for that item
+ * (nothing is read for it).  n <= 2^31 - 1. */
+hpac_status hpac_bs_vjp_ref(int64_t n, const void *const *in, const int32_t *source, const float *grad_call,
+                            const float *grad_put, void *const *grad_in, void *stream);
 
 /* ------------------------------------------------------------------------
  * MLP surrogate: a further approximation technique for HPAC_REGION_BS_PRICE

@@ -35,6 +35,20 @@ enum { kSmall = 0, kLarge = 1, kIni = 2, kFini = 3 };
 
 // ------------------------------------------------------------------ helpers
 
+// Regions with an output that names the item whose evaluation produced the
+// outputs (RegionBSPriceRef): the accurate path writes the item's own index
+// there, as int32 bits; a reused iACT entry carries its source's.
+template <class R, class = void>
+struct HasIndexOut : std::false_type {};
+template <class R>
+struct HasIndexOut<R, std::void_t<decltype(R::kIndexOut)>> : std::true_type {};
+
+template <class R>
+__device__ __forceinline__ void eval_at(const float (&x)[R::kIn], int64_t i, float (&y)[R::kOut]) {
+  R::eval(x, y);
+  if constexpr (HasIndexOut<R>::value) y[R::kIndexOut] = __int_as_float((int)i);
+}
+
 template <class R>
 __device__ __forceinline__ void load_inputs(const KArgs &a, int64_t i, float (&x)[R::kIn]) {
 #pragma unroll
@@ -196,7 +210,7 @@ __global__ void __launch_bounds__(256) k_exact(KArgs a) {
       prefetch<R>(a, g, k + 1, true, xn);
       if (active) {
         float y[R::kOut];
-        R::eval(x, y);
+        eval_at<R>(x, g.item(a, k), y);
         store_outputs<R>(a, g.item(a, k), y);
       }
       if (kStats) {
@@ -420,7 +434,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
 #pragma unroll
       for (int o = 0; o < R::kOut; ++o) y[o] = tab[(arg * E + R::kIn + o) * ws];
     }
-    if (computes) R::eval(x, y);
+    if (computes) eval_at<R>(x, i, y);
     if (active) store_outputs<R>(a, i, y);
     // write phase: one writer per table among the lanes that computed
     const uint64_t cmask = ballot(computes);
@@ -694,6 +708,8 @@ static inline dim3 counted_grid(const KArgs &a, int block) {
   return dim3(g.x < kCountedGrid ? g.x : kCountedGrid);
 }
 
+static_assert(entry_floats<RegionBSPriceRef>() == entry_floats<RegionBSPrice>(), "source-item entries");
+
 int64_t iact_lds_bytes(int region, int block, int table_size, int tables_per_wave) {
   const int E = region == 1 ? entry_floats<RegionBSPriceGrad>() : entry_floats<RegionBSPrice>();
   return (int64_t)(block / kWave) * tables_per_wave * iact_table_stride(E, block, table_size, tables_per_wave) *
@@ -701,21 +717,26 @@ int64_t iact_lds_bytes(int region, int block, int table_size, int tables_per_wav
 }
 
 // (region, column type) -> region type.  Regions: 0 price, 1 price and
-// Jacobian, 2 price in FP16, 3 price at BF16 precision.  Column types: 0 FP32,
-// 1 FP16, 2 BF16.  The half-precision bodies pair with FP32 columns or with
-// columns of their own type; the Jacobian region takes FP32 columns only.
+// Jacobian, 2 price in FP16, 3 price at BF16 precision, 5 price and source
+// item (exact and iACT only).  Column types: 0 FP32, 1 FP16, 2 BF16.  The
+// half-precision bodies pair with FP32 columns or with columns of their own
+// type; the Jacobian and source-item regions take FP32 columns only.
 bool region_dtype_supported(int region, int dtype) {
   switch (region) {
     case 0: return dtype >= 0 && dtype <= 2;
     case 1: return dtype == 0;
+    case 5: return dtype == 0;
     case 2: return dtype == 0 || dtype == 1;
     case 3: return dtype == 0 || dtype == 2;
     default: return false;
   }
 }
 
-template <class F>
+template <bool kIndexRegions = false, class F>
 static hipError_t with_region(int region, int dtype, const F &f) {
+  if constexpr (kIndexRegions) {
+    if (region == 5 && dtype == 0) return f.template go<RegionBSPriceRef>();
+  }
   switch (region * 4 + dtype) {
     case 0: return f.template go<RegionBSPrice>();
     case 1: return f.template go<WithIo<RegionBSPrice, IoF16>>();
@@ -748,7 +769,9 @@ struct ExactL {
   }
 };
 
-hipError_t launch_exact(const LaunchCfg &c, const KArgs &a) { return with_region(c.region, c.dtype, ExactL{c, a}); }
+hipError_t launch_exact(const LaunchCfg &c, const KArgs &a) {
+  return with_region<true>(c.region, c.dtype, ExactL{c, a});
+}
 
 // A dispatch's grid size is a 32-bit count of lanes.
 constexpr int64_t kMaxGridLanes = 0xFFFFFFFFll;
@@ -837,7 +860,7 @@ struct IactL {
 
 hipError_t launch_iact(const LaunchCfg &c, const KArgs &a, int level, int table_size, float threshold,
                        int tables_per_wave) {
-  return with_region(c.region, c.dtype, IactL{c, a, level, table_size, threshold, tables_per_wave});
+  return with_region<true>(c.region, c.dtype, IactL{c, a, level, table_size, threshold, tables_per_wave});
 }
 
 template <class R, int LEVEL, int H>

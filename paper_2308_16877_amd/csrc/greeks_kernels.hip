@@ -42,6 +42,32 @@ __global__ void __launch_bounds__(256) k_bs_adjoint(VjpArgs a) {
   }
 }
 
+// Backward of the by-reference memo: item i's derivatives are those of its
+// source item j = src[i] (itself where the forward computed, the stored
+// entry's source where iACT reused one), recomputed from j's inputs with the
+// forward's region, so they equal bit for bit the Jacobian the price-and-
+// Jacobian region would have stored and reused.  An index outside [0, n)
+// (a column not written by such a forward) gives NaN gradients and reads
+// nothing.
+__global__ void __launch_bounds__(256) k_bs_vjp_ref(VjpArgs a) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+    const float gc = a.gC ? a.gC[i] : 0.0f;
+    const float gp = a.gP ? a.gP[i] : 0.0f;
+    const int64_t j = a.src[i];
+    if (j < 0 || j >= a.n) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) a.gin[k][i] = __builtin_nanf("");
+      continue;
+    }
+    const float x[5] = {a.in[0][j], a.in[1][j], a.in[2][j], a.in[3][j], a.in[4][j]};
+    float y[RegionBSPriceGrad::kOut];
+    RegionBSPriceGrad::eval(x, y);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) a.gin[k][i] = contract2(gc, y[2 + k], gp, y[7 + k]);
+  }
+}
+
 static dim3 grid_items(int64_t n) {
   int64_t blocks = (n + 255) / 256;
   if (blocks > 1 << 20) blocks = 1 << 20;  // grid-stride beyond this
@@ -50,6 +76,11 @@ static dim3 grid_items(int64_t n) {
 
 hipError_t launch_bs_vjp(const VjpArgs &a, hipStream_t stream) {
   hipLaunchKernelGGL(k_bs_vjp, grid_items(a.n), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_bs_vjp_ref(const VjpArgs &a, hipStream_t stream) {
+  hipLaunchKernelGGL(k_bs_vjp_ref, grid_items(a.n), dim3(256), 0, stream, a);
   return hipGetLastError();
 }
 

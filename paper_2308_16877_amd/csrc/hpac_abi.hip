@@ -37,6 +37,7 @@ bool region_shape(int region, RegionShape *s) {
     case HPAC_REGION_BS_PRICE_F16:
     case HPAC_REGION_BS_PRICE_BF16: *s = {5, 2}; return true;
     case HPAC_REGION_BS_PRICE_GRAD: *s = {5, 12}; return true;
+    case HPAC_REGION_BS_PRICE_REF: *s = {5, 3}; return true;
     default: return false;
   }
 }
@@ -61,6 +62,8 @@ hpac_status check_io(const char *fn, const hpac_region_io *io, hpac::KArgs *a, h
     return fail(HPAC_EUNSUPPORTED, "%s: region %d does not take columns of dtype %d", fn, io->region, io->dtype);
   const uintptr_t align = io->dtype == HPAC_F32 ? 4 : 2;
   if (io->n < 0 || io->n > kMaxItems) return fail(HPAC_EINVAL, "%s: n = %lld out of range [0, 2^40]", fn, (long long)io->n);
+  if (io->region == HPAC_REGION_BS_PRICE_REF && io->n > INT32_MAX)
+    return fail(HPAC_EINVAL, "%s: the source-item region indexes at most 2^31-1 items", fn);
   if (io->n_in != rs.n_in || io->n_out != rs.n_out)
     return fail(HPAC_EINVAL, "%s: region %d takes %d inputs and %d outputs, got %d and %d", fn, io->region, rs.n_in,
                 rs.n_out, io->n_in, io->n_out);
@@ -212,6 +215,8 @@ hpac_status hpac_taf(const hpac_region_io *io, int32_t history_size, int32_t pre
   hpac::LaunchCfg c;
   hpac_status s = check_io(fn, io, &a, &c);
   if (s != HPAC_OK) return s;
+  if (io->region == HPAC_REGION_BS_PRICE_REF)
+    return fail(HPAC_EUNSUPPORTED, "%s: the source-item region is provided for hpac_exact and hpac_iact", fn);
   if (history_size < 1 || history_size > 8)
     return fail(HPAC_EINVAL, "%s: history_size = %d out of range [1, 8]", fn, history_size);
   if (prediction_size < 1) return fail(HPAC_EINVAL, "%s: prediction_size = %d must be >= 1", fn, prediction_size);
@@ -227,6 +232,8 @@ hpac_status hpac_perfo(const hpac_region_io *io, int32_t kind, int32_t param, in
   hpac::LaunchCfg c;
   hpac_status s = check_io(fn, io, &a, &c);
   if (s != HPAC_OK) return s;
+  if (io->region == HPAC_REGION_BS_PRICE_REF)
+    return fail(HPAC_EUNSUPPORTED, "%s: the source-item region is provided for hpac_exact and hpac_iact", fn);
   if (kind < HPAC_PERFO_SMALL || kind > HPAC_PERFO_FINI) return fail(HPAC_EINVAL, "%s: unknown kind %d", fn, kind);
   if (param < 0) return fail(HPAC_EINVAL, "%s: param = %d must be >= 0", fn, param);
   if ((kind == HPAC_PERFO_INI || kind == HPAC_PERFO_FINI) && param > 100)
@@ -262,6 +269,19 @@ hpac_status hpac_bs_vjp(int64_t n, const void *const *jacobian, const float *gra
   if (s != HPAC_OK || n == 0) return s;
   for (int j = 0; j < 10; ++j) a.jac[j] = (const float *)jacobian[j];
   return hip_status(fn, hpac::launch_bs_vjp(a, (hipStream_t)stream));
+}
+
+hpac_status hpac_bs_vjp_ref(int64_t n, const void *const *in, const int32_t *source, const float *grad_call,
+                            const float *grad_put, void *const *grad_in, void *stream) {
+  const char *fn = "hpac_bs_vjp_ref";
+  hpac::VjpArgs a = {};
+  if (n > INT32_MAX) return fail(HPAC_EINVAL, "%s: at most 2^31-1 items (int32 source indices)", fn);
+  hpac_status s = check_vjp(fn, n, in, 5, grad_call, grad_put, grad_in, &a);
+  if (s != HPAC_OK || n == 0) return s;
+  if (!source || (uintptr_t)source % 4) return fail(HPAC_EINVAL, "%s: source is NULL or misaligned", fn);
+  for (int j = 0; j < 5; ++j) a.in[j] = (const float *)in[j];
+  a.src = source;
+  return hip_status(fn, hpac::launch_bs_vjp_ref(a, (hipStream_t)stream));
 }
 
 hpac_status hpac_bs_adjoint(int64_t n, const void *const *in, const float *grad_call, const float *grad_put,

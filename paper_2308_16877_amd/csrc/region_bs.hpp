@@ -83,6 +83,27 @@ struct RegionBSPrice {
   }
 };
 
+// Region: inputs (S, K, T, r, v) -> (call, put, source item).  The prices of
+// RegionBSPrice; output kIndexOut is the index of the item whose evaluation
+// produced them (its bits stored in the FP32 column), filled in by the
+// kernels: the item itself on an accurate path, the stored entry's source
+// item when iACT reuses an entry.  A backward pass can then recompute the
+// derivatives at the source item's inputs: the reused gradient is reached by
+// reference instead of being carried as ten columns.
+struct RegionBSPriceRef {
+  static constexpr int kIn = 5;
+  static constexpr int kOut = 3;
+  static constexpr int kIndexOut = 2;
+  using io = IoF32;
+  __device__ __forceinline__ static void eval(const float (&x)[kIn], float (&y)[kOut]) {
+    float p[2];
+    RegionBSPrice::eval(x, p);
+    y[0] = p[0];
+    y[1] = p[1];
+    y[2] = 0.0f;
+  }
+};
+
 // Region: inputs (S, K, T, r, v) -> (call, put, dC/dx[5], dP/dx[5]), x in
 // input order.  Closed-form sensitivities; the put row is written with the
 // tail probabilities (dP/dS = -N(-d1), dP/dK = e^{-rT} N(-d2), ...), the same

@@ -16,8 +16,9 @@ HPAC_OK, HPAC_EINVAL, HPAC_EUNSUPPORTED, HPAC_EHIP, HPAC_ENUMERIC = 0, -1, -2, -
 HYDRO_BAD_VOLUME, HYDRO_BAD_DT = 1, 2
 REGION_BS_PRICE, REGION_BS_PRICE_GRAD, REGION_BS_PRICE_F16, REGION_BS_PRICE_BF16 = 0, 1, 2, 3
 REGION_BINOMIAL = 4
+REGION_BS_PRICE_REF = 5
 REGION_SHAPE = {REGION_BS_PRICE: (5, 2), REGION_BS_PRICE_GRAD: (5, 12), REGION_BS_PRICE_F16: (5, 2),
-                REGION_BS_PRICE_BF16: (5, 2), REGION_BINOMIAL: (5, 2)}
+                REGION_BS_PRICE_BF16: (5, 2), REGION_BINOMIAL: (5, 2), REGION_BS_PRICE_REF: (5, 3)}
 F32, F16, BF16 = 0, 1, 2
 LEVEL_THREAD, LEVEL_WAVE, LEVEL_BLOCK = 0, 1, 2
 LEVELS = {"thread": LEVEL_THREAD, "wave": LEVEL_WAVE, "warp": LEVEL_WAVE, "block": LEVEL_BLOCK, "team": LEVEL_BLOCK}
@@ -114,6 +115,8 @@ def lib():
         f.restype = i32
     L.hpac_bs_vjp.argtypes = [i64, PP, vp, vp, PP, vp]
     L.hpac_bs_adjoint.argtypes = [i64, PP, vp, vp, PP, vp]
+    L.hpac_bs_vjp_ref.argtypes = [i64, PP, vp, vp, vp, PP, vp]
+    L.hpac_bs_vjp_ref.restype = i32
     for f in (L.hpac_exact, L.hpac_iact, L.hpac_taf, L.hpac_perfo, L.hpac_probe_copy, L.hpac_bs_vjp,
               L.hpac_bs_adjoint):
         f.restype = i32
@@ -220,7 +223,14 @@ def make_io(inputs, outputs, n=None, region=None, items_per_lane=1, block_size=0
     if dtype is None:
         first = next((c for c in inputs + outputs if not isinstance(c, int)), None)
         dtype = F32 if first is None else _dtype_code(first)
-    for c in inputs + outputs:
+    cols = inputs + outputs
+    if region == REGION_BS_PRICE_REF and len(outputs) == 3:
+        # the source-item column holds int32 indices
+        _check_buf(outputs[2], n, "i32", "source column")
+        if not isinstance(outputs[2], int) and outputs[2].numel() != n:
+            raise ValueError("the source column must hold n elements")
+        cols = inputs + outputs[:2]
+    for c in cols:
         _check_column(c, n, dtype)
     if trace is not None and not isinstance(trace, int):
         if region == REGION_BINOMIAL:
@@ -342,6 +352,19 @@ def hpac_bs_adjoint(inputs, grad_call, grad_put, grad_in, n=None, stream=None):
     gp, keep2 = _ptr_array(grad_in)
     st = _stream(stream, list(grad_in))
     _call("hpac_bs_adjoint", lib().hpac_bs_adjoint(n, ip, _addr(grad_call), _addr(grad_put), gp, st))
+
+
+def hpac_bs_vjp_ref(inputs, source, grad_call, grad_put, grad_in, n=None, stream=None):
+    """The contraction with the derivatives recomputed at each item's source
+    item (the int32 column a forward on REGION_BS_PRICE_REF wrote)."""
+    n = grad_in[0].numel() if n is None else n
+    for c in list(inputs) + list(grad_in) + [g for g in (grad_call, grad_put) if g is not None]:
+        _check_column(c, n)
+    _check_buf(source, n, "i32", "source")
+    ip, keep1 = _ptr_array(inputs)
+    gp, keep2 = _ptr_array(grad_in)
+    st = _stream(stream, list(grad_in))
+    _call("hpac_bs_vjp_ref", lib().hpac_bs_vjp_ref(n, ip, _addr(source), _addr(grad_call), _addr(grad_put), gp, st))
 
 
 def hpac_surrogate(inputs, outputs, params, norm, box_lo, box_hi, queue, queue_count, stream=None, n=None):

@@ -307,3 +307,20 @@ def test_short_or_mistyped_buffers_are_rejected_by_the_binding():
     with pytest.raises(ValueError, match="dst holds"):
         hpac.hpac_probe_copy(FAKE, torch.zeros(3, dtype=torch.float32), 16)
 
+
+def test_source_item_region_arguments():
+    """The price-and-source region: 3 outputs, exact and iACT only, int32
+    indices (n <= 2^31 - 1); its backward checks its source column."""
+    E, U = hpac.HPAC_EINVAL, hpac.HPAC_EUNSUPPORTED
+    ref = dict(region=hpac.REGION_BS_PRICE_REF, outputs=[FAKE] * 3)
+    expect(E, hpac.hpac_exact, **io(region=hpac.REGION_BS_PRICE_REF))  # 2 outputs for a 3-output region
+    expect(U, hpac.hpac_taf, history_size=4, prediction_size=4, rsd_threshold=0.1, **io(**ref))
+    expect(U, hpac.hpac_perfo, kind="small", param=10, **io(**ref))
+    expect(E, hpac.hpac_iact, table_size=8, threshold=0.1, **io(n=2**31, items_per_lane=64, **ref))
+    expect(E, hpac.hpac_bs_vjp_ref, [FAKE] * 5, 0, FAKE, FAKE, [FAKE] * 5, n=10)
+    expect(E, hpac.hpac_bs_vjp_ref, [FAKE] * 5, FAKE + 2, FAKE, FAKE, [FAKE] * 5, n=10)
+    expect(E, hpac.hpac_bs_vjp_ref, [FAKE] * 5, FAKE, FAKE, FAKE, [FAKE] * 5, n=2**31)
+    import torch
+    with pytest.raises(ValueError, match="source"):
+        hpac.hpac_exact([FAKE] * 5, [FAKE, FAKE, torch.zeros(999, dtype=torch.int32)], n=1000,
+                        region=hpac.REGION_BS_PRICE_REF)

@@ -134,6 +134,75 @@ def test_iact_grad_block_sizes_match_oracle(block):
     check_outputs(y, ora["out"], ora["scale"], what="iact grad block %d" % block)
 
 
+@pytest.mark.parametrize("case", IACT_GRAD_CASES, ids=[c[0] for c in IACT_GRAD_CASES])
+def test_memo_by_reference_equals_saved_jacobian(case):
+    """iACT on the price-and-source region carries 4 bytes per item (the
+    source item's index) instead of ten Jacobian columns: the same decisions
+    and prices, bit for bit, as iACT on the price-and-Jacobian region; the
+    source of every item equals the oracle's (its engine run with the item
+    index as an output reuses entries exactly as it reuses prices); and the
+    backward, recomputing the derivatives at each source item, equals the
+    saved-Jacobian VJP bit for bit."""
+    name, mk, ipt, t, theta = case
+    say("memo by reference", name)
+    x = mk()
+    n = x.shape[1]
+    xd = to_dev(x)
+    y12, tr12, _ = run("iact", xd, 12, ipt, region=hpac.REGION_BS_PRICE_GRAD, table_size=t, threshold=theta)
+    C, P = (torch.full((n,), SENTINEL, dtype=torch.float32, device=DEV) for _ in range(2))
+    src = torch.full((n,), -1, dtype=torch.int32, device=DEV)
+    tr = torch.zeros(hpac.hpac_trace_entries(n, ipt), dtype=torch.int32, device=DEV)
+    hpac.hpac_iact(xd, [C, P, src], t, theta, items_per_lane=ipt, region=hpac.REGION_BS_PRICE_REF, trace=tr)
+    torch.cuda.synchronize()
+    assert np.array_equal(tr.cpu().numpy().view(np.uint32), tr12)
+    assert np.array_equal(C.cpu().numpy().astype(np.float64), y12[0])
+    assert np.array_equal(P.cpu().numpy().astype(np.float64), y12[1])
+    yv, sv = oracle.region_values_f32out(x)
+    ora = oracle.iact(x, np.vstack([yv, np.arange(n, dtype=np.float64)]), None, ipt, t, theta)
+    s = src.cpu().numpy()
+    assert np.array_equal(s, ora["out"][2].astype(np.int64))
+    approx = s != np.arange(n)
+    say("  %.3f of the items reuse another item's prices and derivatives" % approx.mean())
+    g = np.random.default_rng(9).standard_normal((2, n)).astype(np.float32)
+    gC, gP = (torch.from_numpy(g[i]).to(DEV) for i in range(2))
+    J = [torch.from_numpy(y12[2 + j].astype(np.float32)).to(DEV) for j in range(10)]
+    a = [torch.empty(n, dtype=torch.float32, device=DEV) for _ in range(5)]
+    b = [torch.empty(n, dtype=torch.float32, device=DEV) for _ in range(5)]
+    hpac.hpac_bs_vjp(J, gC, gP, a)
+    hpac.hpac_bs_vjp_ref(xd, src, gC, gP, b)
+    torch.cuda.synchronize()
+    for j in range(5):
+        assert torch.equal(a[j], b[j]), j
+
+
+def test_exact_source_column_and_bad_indices():
+    """hpac_exact on the price-and-source region writes each item's own
+    index; the by-reference backward turns an index outside [0, n) into NaN
+    gradients for that item and reads nothing for it."""
+    n = 10007
+    x = inputs.portfolio(n, 1024)
+    xd = to_dev(x)
+    C, P = (torch.empty(n, dtype=torch.float32, device=DEV) for _ in range(2))
+    src = torch.full((n,), -1, dtype=torch.int32, device=DEV)
+    hpac.hpac_exact(xd, [C, P, src], items_per_lane=3, region=hpac.REGION_BS_PRICE_REF)
+    torch.cuda.synchronize()
+    assert np.array_equal(src.cpu().numpy(), np.arange(n))
+    bad = src.clone()
+    bad[5], bad[6], bad[7] = -3, n, 2 ** 31 - 1
+    ones = torch.ones(n, dtype=torch.float32, device=DEV)
+    a = [torch.empty(n, dtype=torch.float32, device=DEV) for _ in range(5)]
+    b = [torch.empty(n, dtype=torch.float32, device=DEV) for _ in range(5)]
+    hpac.hpac_bs_adjoint(xd, ones, None, a)
+    hpac.hpac_bs_vjp_ref(xd, bad, ones, None, b)
+    torch.cuda.synchronize()
+    for j in range(5):
+        bj = b[j].cpu().numpy()
+        assert np.all(np.isnan(bj[5:8]))
+        keep = np.ones(n, bool)
+        keep[5:8] = False
+        assert np.array_equal(bj[keep], a[j].cpu().numpy()[keep])
+
+
 def test_vjp_contracts_the_saved_jacobian():
     n = 100003
     x = inputs.portfolio(n, 1024)
@@ -172,12 +241,12 @@ def test_recomputing_adjoint_equals_vjp_of_exact_jacobian():
         assert torch.equal(a[j], b[j])
 
 
-@pytest.mark.parametrize("technique", ["exact", "iact"])
+@pytest.mark.parametrize("technique", ["exact", "iact", "iact_jacobian"])
 def test_autograd_greeks_against_closed_forms(technique):
     n = 65536
     x = inputs.portfolio(n, 1024) if technique == "exact" else inputs.periodic(n, 2, jitter=1e-3)
     xt = [torch.from_numpy(c).to(DEV).requires_grad_(True) for c in x]
-    params = dict(table_size=16, threshold=0.05) if technique == "iact" else None
+    params = dict(table_size=16, threshold=0.05) if technique != "exact" else None
     C, P = bs_prices(*xt, technique=technique, params=params)
     gcall = torch.autograd.grad(C.sum(), xt, retain_graph=True)
     gput = torch.autograd.grad(P.sum(), xt)

@@ -304,3 +304,68 @@ def test_numeric_failure_is_reported():
     ok.run(150)
     ok.check()
     assert int(ok.status.item()) == 0
+
+
+CONFIG_TECHS = [
+    # the bench-reported techniques at the configuration's mesh (90^3, 500 steps)
+    ("exact", Tech()),
+    ("eos_taf_thread_h4_p2_0.001", Tech(eos=(4, 2, 0.001, "thread"))),
+    ("eos_taf_wave_h4_0.01", Tech(eos=(4, 4, 0.01))),
+    ("hg_perfo_small_M10", Tech(perfo=("small", 10, 1))),
+]
+
+
+@pytest.mark.parametrize("name,tech", CONFIG_TECHS, ids=[c[0] for c in CONFIG_TECHS])
+def test_config_mesh_late_step_replay(name, tech):
+    """The 90^3 blast run on the GPU to steps 100, 250 and 499 of its 500,
+    each of those steps replayed by the FP64 oracle from the GPU's state:
+    every field within 1e-5 of its scale and TAF decisions equal wherever
+    the vote is not fragile (the statistic within a relative 1e-3 of the
+    threshold, for the oracle's FP64 region values against the GPU's FP32
+    ones).  Wave-level EOS TAF is unstable on this blast (its free run
+    leaves the exact trajectory by orders of magnitude, in the FP64 oracle
+    as on the GPU); the replay shows that each of its steps is still the
+    method's step, not a kernel error."""
+    h = Hydro(90, tech=tech)
+    for target in (100, 250, 499):
+        h.run(target - h.steps)
+        errs, dec, _ = replay_step(h)
+        say("90^3 %s step %d: %s" % (name, target, {f: "%.1e" % e for f, e in errs.items()}))
+        check_errs(errs, "90^3 %s step %d" % (name, target))
+        for region, (gd, od, frag) in dec.items():
+            assert np.all((gd == od) | frag), (region, target, int(((gd != od) & ~frag).sum()))
+            say("  %s decisions: %d of %d groups approximate, %d fragile" % (
+                region, int((gd == 1).sum()), gd.size, int(frag.sum())))
+
+
+QOI_TECHS = [
+    ("eos_taf_thread_h4_p2_0.001", Tech(eos=(4, 2, 0.001, "thread"))),
+    ("eos_taf_thread_h2_p2_0.001", Tech(eos=(2, 2, 0.001, "thread"))),
+    ("hg_taf_thread_h4_p4_0.01", Tech(hg=(4, 4, 0.01, "thread"))),
+    ("hg_perfo_small_M10", Tech(perfo=("small", 10, 1))),
+    ("hg_perfo_fini_20", Tech(perfo=("fini", 20, 1))),
+]
+
+
+@pytest.mark.parametrize("name,tech", QOI_TECHS, ids=[c[0] for c in QOI_TECHS])
+def test_whole_run_qoi_error_matches_oracle(name, tech):
+    """Well-conditioned whole runs (16^3 x 100 steps and 24^3 x 150): the
+    quantity-of-interest error each technique causes (origin energy against
+    the exact run of the same precision) on the GPU equals the oracle's own
+    free run's within 1e-4 absolute."""
+    for n, steps in ((16, 100), (24, 150)):
+        qg, qo = {}, {}
+        for key, t in (("exact", Tech()), (name, tech)):
+            h = Hydro(n, tech=t)
+            h.run(steps)
+            torch.cuda.synchronize()
+            qg[key] = h.origin_energy()
+            kw = oracle_tech(t)
+            s = oracle.hydro_init(n, sedov_origin_energy(n), eos_h=t.eos[0] if t.eos else 0,
+                                  hg_h=t.hg[0] if t.hg else 0)
+            for k in range(steps):
+                oracle.hydro_step(s, k, **kw)
+            qo[key] = float(s.e[0])
+        eg, eo = abs(qg[name] / qg["exact"] - 1), abs(qo[name] / qo["exact"] - 1)
+        say("%s n=%d: QoI error GPU %.3e oracle %.3e" % (name, n, eg, eo))
+        assert abs(eg - eo) <= 1e-4
