@@ -598,10 +598,13 @@ def binomial_leg(torch, hpac, n=65536, steps=512):
 
 
 HYDRO_TECHS = {
-    # name: hydro technique arguments (the TAF grid is in HYDRO_SWEEP)
+    # name: hydro technique arguments (the TAF grid is in HYDRO_SWEEP); the
+    # FP64 oracle's run of each is stored under the same name
     "exact": {},
     "eos_taf_thread_h4_p2_0.001": dict(eos=(4, 2, 0.001, "thread")),
+    "eos_taf_wave_h4_p4_0.01": dict(eos=(4, 4, 0.01, "wave")),
     "hg_perfo_small_M2_ipt2": dict(perfo=("small", 2, 2)),
+    "hg_perfo_small_M10": dict(perfo=("small", 10, 1)),
     "hg_perfo_fini_20": dict(perfo=("fini", 20, 1)),
     "hg_perfo_ini_20": dict(perfo=("ini", 20, 1)),
 }
@@ -614,10 +617,12 @@ def hydro_leg(torch, n=90, steps=500):
     the FP64 oracle's stored run of the same configuration."""
     from paper_2308_16877_amd.hydro import Hydro, Tech
     golden = os.path.join(ROOT, "tests", "golden", "hydro_sedov90_qoi.json")
-    ref64 = None
+    ref64, tech64 = None, {}
     if n == 90 and steps == 500 and os.path.exists(golden):
         with open(golden) as f:
-            ref64 = json.load(f)["records"][-1]["origin_energy"]
+            g = json.load(f)
+        ref64 = g["records"][-1]["origin_energy"]
+        tech64 = {k: v["records"][-1]["origin_energy"] for k, v in g.get("techniques", {}).items()}
     res = {}
     base = None
     for name, kw in HYDRO_TECHS.items():
@@ -634,10 +639,13 @@ def hydro_leg(torch, n=90, steps=500):
         if base is None:
             base = (ms, q)
         ie, ke = h.energy()
+        q64 = tech64.get(name)
         res[name] = {"ms_per_step": ms / steps, "element_steps_per_s": n ** 3 * steps / (ms * 1e-3),
                      "speedup_vs_exact": base[0] / ms, "origin_energy": q,
                      "qoi_err_vs_exact_gpu": abs(q / base[1] - 1),
                      "qoi_err_vs_fp64_oracle": abs(q / ref64 - 1) if ref64 else None,
+                     # the technique's own QoI error in the FP64 oracle (its run against the oracle's exact run)
+                     "oracle_qoi_err_vs_oracle_exact": abs(q64 / ref64 - 1) if q64 is not None and ref64 else None,
                      "total_energy": ie + ke, "time": h.time()}
         del h
     sweep = hydro_sweep(torch, res["exact"]["ms_per_step"], res["exact"]["origin_energy"], ref64, n, steps)
