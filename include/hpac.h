@@ -370,6 +370,21 @@ hpac_status hpac_hydro_init(const hpac_hydro_params *params, double e_origin, co
 hpac_status hpac_hydro_step(const hpac_hydro_params *params, const hpac_hydro_tech *tech, int32_t step,
                             const hpac_hydro_state *state, int8_t *dec_eos, int8_t *dec_hg, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * timestep as hpac_hydro_step, with the time-step reduction's partial minima
+ * kept in the library's own device array (512 KiB, allocated with the
+ * library's code object on each GPU it runs on and held until the process
+ * ends) instead of state->dt_partials, which is ignored and may be NULL.
+ * Meshes of n <= HPAC_HYDRO_NOALLOC_MAX_N elements per side; larger n is
+ * rejected with HPAC_EINVAL.  The call allocates nothing.  The array is
+ * shared by every call on that GPU: calls that overlap on one GPU (on
+ * different streams, or from several threads) race on it, so serialise them;
+ * each call writes every entry it reads before reading it. */
+#define HPAC_HYDRO_NOALLOC_MAX_N 256
+hpac_status hpac_hydro_step_noalloc(const hpac_hydro_params *params, const hpac_hydro_tech *tech, int32_t step,
+                                    const hpac_hydro_state *state, int8_t *dec_eos, int8_t *dec_hg, void *stream);
+
 /* `steps` (>= 0) timesteps with indices first_step, first_step + 1, ...:
  * the same launches as that many hpac_hydro_step calls with u and unew
  * swapped between them, issued from one host loop (no decision records).

@@ -14,6 +14,9 @@
 
 static_assert(hpac::kHydroBadVolume == HPAC_HYDRO_BAD_VOLUME && hpac::kHydroBadDt == HPAC_HYDRO_BAD_DT,
               "hydro flag bits");
+static_assert((((int64_t)HPAC_HYDRO_NOALLOC_MAX_N * HPAC_HYDRO_NOALLOC_MAX_N * HPAC_HYDRO_NOALLOC_MAX_N + 63) / 64 * 64 +
+               255) / 256 <= hpac::kHydroScratchPartials,
+              "the allocation-free hydro step's scratch array holds the largest mesh it accepts");
 
 namespace {
 
@@ -475,7 +478,7 @@ static hpac_status check_hydro_params(const char *fn, const hpac_hydro_params *P
   return HPAC_OK;
 }
 
-static hpac_status check_hydro_state(const char *fn, const hpac_hydro_state *S) {
+static hpac_status check_hydro_state(const char *fn, const hpac_hydro_state *S, bool own_partials = true) {
   if (!S) return fail(HPAC_EINVAL, "%s: state is NULL", fn);
   for (int d = 0; d < 3; ++d)
     if (!aligned4(S->x[d]) || !aligned4(S->u[d]) || !aligned4(S->unew[d]))
@@ -483,8 +486,9 @@ static hpac_status check_hydro_state(const char *fn, const hpac_hydro_state *S) 
   const float *f[] = {S->mnode, S->e, S->p, S->q, S->c, S->vol, S->mass, S->force};
   for (const float *x : f)
     if (!aligned4(x)) return fail(HPAC_EINVAL, "%s: a mesh field is NULL or misaligned", fn);
-  if (!S->clock || (uintptr_t)S->clock % 8 || !S->dt_partials || (uintptr_t)S->dt_partials % 8)
-    return fail(HPAC_EINVAL, "%s: clock or dt_partials is NULL or misaligned", fn);
+  if (!S->clock || (uintptr_t)S->clock % 8) return fail(HPAC_EINVAL, "%s: clock is NULL or misaligned", fn);
+  if (own_partials && (!S->dt_partials || (uintptr_t)S->dt_partials % 8))
+    return fail(HPAC_EINVAL, "%s: dt_partials is NULL or misaligned", fn);
   if (!aligned4(S->status)) return fail(HPAC_EINVAL, "%s: status is NULL or misaligned", fn);
   return HPAC_OK;
 }
@@ -569,9 +573,10 @@ hpac_status hpac_hydro_init(const hpac_hydro_params *params, double e_origin, co
 // Checks of a hydro step's arguments and its kernel arguments and modes.
 static hpac_status hydro_prepare(const char *fn, const hpac_hydro_params *params, const hpac_hydro_tech *tech,
                                  int32_t step, const hpac_hydro_state *state, int8_t *dec_eos, int8_t *dec_hg,
-                                 hpac::HydroArgs *out, int *hg_mode, int *eos_mode_out) {
+                                 hpac::HydroArgs *out, int *hg_mode, int *eos_mode_out,
+                                 bool own_partials = true) {
   hpac_status st = check_hydro_params(fn, params);
-  if (st == HPAC_OK) st = check_hydro_state(fn, state);
+  if (st == HPAC_OK) st = check_hydro_state(fn, state, own_partials);
   if (st != HPAC_OK) return st;
   if (!tech) return fail(HPAC_EINVAL, "%s: tech is NULL", fn);
   if (step < 0) return fail(HPAC_EINVAL, "%s: step = %d must be >= 0", fn, step);
@@ -640,6 +645,23 @@ hpac_status hpac_hydro_step(const hpac_hydro_params *params, const hpac_hydro_te
   const hpac_status st = hydro_prepare(fn, params, tech, step, state, dec_eos, dec_hg, &a, &mode, &eos_mode);
   if (st != HPAC_OK) return st;
   return hip_status(fn, hpac::launch_hydro_step(a, mode, eos_mode, (hipStream_t)stream));
+}
+
+hpac_status hpac_hydro_step_noalloc(const hpac_hydro_params *params, const hpac_hydro_tech *tech, int32_t step,
+                                    const hpac_hydro_state *state, int8_t *dec_eos, int8_t *dec_hg, void *stream) {
+  const char *fn = "hpac_hydro_step_noalloc";
+  if (params && params->n > HPAC_HYDRO_NOALLOC_MAX_N)
+    return fail(HPAC_EINVAL, "%s: n = %d exceeds the %d elements per side the library's scratch array holds", fn,
+                params->n, HPAC_HYDRO_NOALLOC_MAX_N);
+  hpac::HydroArgs a;
+  int mode = 0, eos_mode = 0;
+  const hpac_status st = hydro_prepare(fn, params, tech, step, state, dec_eos, dec_hg, &a, &mode, &eos_mode, false);
+  if (st != HPAC_OK) return st;
+  if (hpac::hydro_partials(a.E) > hpac::kHydroScratchPartials)
+    return fail(HPAC_EINVAL, "%s: the mesh needs more partial minima than the scratch array holds", fn);
+  hipError_t e = hpac::hydro_scratch((hipStream_t)stream, &a.dt_partials);
+  if (e == hipSuccess) e = hpac::launch_hydro_step(a, mode, eos_mode, (hipStream_t)stream);
+  return hip_status(fn, e);
 }
 
 hpac_status hpac_hydro_run(const hpac_hydro_params *params, const hpac_hydro_tech *tech, int32_t first_step,

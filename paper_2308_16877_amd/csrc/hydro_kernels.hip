@@ -33,6 +33,8 @@
 #include "launch_hydro.hpp"
 #include "wave.hpp"
 
+#include <mutex>
+
 namespace hpac {
 
 namespace {
@@ -670,6 +672,41 @@ __global__ void __launch_bounds__(256) k_hydro_eos(HydroArgs a) {
 int64_t hydro_lanes(int64_t E, int ipt) { return 64 * (((E + ipt - 1) / ipt + 63) / 64); }
 
 int64_t hydro_partials(int64_t E) { return (hydro_lanes(E, 1) + 255) / 256; }
+
+// Partial time-step minima of the allocation-free step: one double per
+// workgroup of the force kernel, held in a file-scope device array rather
+// than a caller buffer.  Every GPU the library runs on holds its own copy,
+// at its own address, until the process ends.  In host code `scratch` names
+// a host-side stand-in, never passed to a kernel: its device address is
+// looked up once per device, with that device current, and kept.
+static __device__ __align__(256) double scratch[kHydroScratchPartials];
+
+hipError_t hydro_scratch(hipStream_t stream, double **ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static double *addr[kMaxDevices] = {};
+  int cur = 0, dev = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  dev = cur;
+  if (stream && (e = hipStreamGetDevice(stream, &dev)) != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    if (dev != cur && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (dev != cur) {
+      const hipError_t r = hipSetDevice(cur);
+      if (e == hipSuccess) e = r;
+    }
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = (double *)p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
+}
 
 hipError_t launch_hydro_init(const HydroArgs &a, double e_origin, double dt0, hipStream_t s) {
   hipLaunchKernelGGL(k_hydro_init_elem, dim3((unsigned)((a.E + 255) / 256)), dim3(256), 0, s, a, e_origin);

@@ -39,6 +39,12 @@ struct HydroArgs {
 constexpr int32_t kHydroBadVolume = 1, kHydroBadDt = 2;
 int64_t hydro_lanes(int64_t E, int ipt);
 int64_t hydro_partials(int64_t E);
+// Size of the library's own partial-minimum array (the allocation-free
+// step's scratch): enough for meshes of up to 256^3 elements.
+constexpr int64_t kHydroScratchPartials = 65536;
+// Device address of that array on `stream`'s device (the current device for
+// the null stream), looked up on the first call per device.
+hipError_t hydro_scratch(hipStream_t stream, double **ptr);
 hipError_t launch_hydro_init(const HydroArgs &a, double e_origin, double dt0, hipStream_t stream);
 hipError_t launch_hydro_step(const HydroArgs &a, int hg_mode, int eos_mode, hipStream_t stream);
 

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(PKG, "libhpac.so")
 
 HPAC_OK, HPAC_EINVAL, HPAC_EUNSUPPORTED, HPAC_EHIP, HPAC_ENUMERIC = 0, -1, -2, -3, -4
 HYDRO_BAD_VOLUME, HYDRO_BAD_DT = 1, 2
+HYDRO_NOALLOC_MAX_N = 256
 REGION_BS_PRICE, REGION_BS_PRICE_GRAD, REGION_BS_PRICE_F16, REGION_BS_PRICE_BF16 = 0, 1, 2, 3
 REGION_BINOMIAL = 4
 REGION_BS_PRICE_REF = 5
@@ -131,6 +132,8 @@ def lib():
     L.hpac_hydro_init.restype = i32
     L.hpac_hydro_step.argtypes = [HP, HT, i32, HS, vp, vp, vp]
     L.hpac_hydro_step.restype = i32
+    L.hpac_hydro_step_noalloc.argtypes = [HP, HT, i32, HS, vp, vp, vp]
+    L.hpac_hydro_step_noalloc.restype = i32
     L.hpac_hydro_run.argtypes = [HP, HT, i32, i32, HS, vp]
     L.hpac_hydro_run.restype = i32
     L.hpac_hydro_check.argtypes = [HS, vp]
@@ -478,6 +481,16 @@ def hpac_hydro_step(params, tech, step, state, dec_eos=None, dec_hg=None, stream
     _call("hpac_hydro_step", lib().hpac_hydro_step(ctypes.byref(params), ctypes.byref(tech), int(step),
                                                    ctypes.byref(state), _addr(dec_eos), _addr(dec_hg),
                                                    _torch_stream(stream)))
+
+
+def hpac_hydro_step_noalloc(params, tech, step, state, dec_eos=None, dec_hg=None, stream=None):
+    if tech.eos_history:
+        _check_buf(dec_eos, hpac_hydro_groups(params.n, tech.eos_level), "i8", "dec_eos")
+    if tech.hg_history:
+        _check_buf(dec_hg, hpac_hydro_groups(params.n, tech.hg_level), "i8", "dec_hg")
+    _call("hpac_hydro_step_noalloc",
+          lib().hpac_hydro_step_noalloc(ctypes.byref(params), ctypes.byref(tech), int(step), ctypes.byref(state),
+                                        _addr(dec_eos), _addr(dec_hg), _torch_stream(stream)))
 
 
 def hpac_hydro_run(params, tech, first_step, steps, state, stream=None):

@@ -93,10 +93,13 @@ class Hydro:
             setattr(s, f, t.data_ptr() if t is not None else None)
         self.state = s
 
-    def step(self, record=False, stream=None):
-        """One timestep (index = number of steps taken so far)."""
-        hpac.hpac_hydro_step(self.params, self.tech.c, self.steps, self.state,
-                             self.dec_eos if record else None, self.dec_hg if record else None, stream)
+    def step(self, record=False, stream=None, noalloc=False):
+        """One timestep (index = number of steps taken so far); noalloc: by
+        hpac_hydro_step_noalloc, the time-step partials in the library's own
+        scratch array."""
+        fn = hpac.hpac_hydro_step_noalloc if noalloc else hpac.hpac_hydro_step
+        fn(self.params, self.tech.c, self.steps, self.state,
+           self.dec_eos if record else None, self.dec_hg if record else None, stream)
         self._swap_velocities()
         self.steps += 1
 

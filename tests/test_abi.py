@@ -211,6 +211,14 @@ def test_invalid_hydro_arguments_are_rejected():
     expect(E, hrun, P, T, -1, 1, S)
     expect(E, hrun, hydro_params(n=0), T, 0, 1, S)
     expect(E, hrun, P, hydro_tech(hg_history=2, hg_prediction=2), 0, 1, hydro_state(whg=0))
+    # the allocation-free step: its own mesh limit, the same checks otherwise
+    hna = lambda *a: hpac.hpac_hydro_step_noalloc(*a, stream=0)
+    msg = expect(E, hna, hydro_params(n=hpac.HYDRO_NOALLOC_MAX_N + 1), T, 0, hydro_state(dt_partials=0))
+    assert "scratch" in msg
+    expect(E, hna, hydro_params(n=0), T, 0, hydro_state(dt_partials=0))
+    expect(E, hna, P, T, 0, hydro_state(e=0, dt_partials=0))
+    expect(E, hna, P, T, -1, hydro_state(dt_partials=0))
+    expect(E, hna, P, hydro_tech(eos_history=2, eos_prediction=2), 0, hydro_state(weos=0, dt_partials=0))
 
 
 def bo_io(**kw):
