@@ -10,6 +10,8 @@ profiles/.
 The optional a:b keeps dispatches a..b-1 of the kernel, in dispatch order
 (the counter probe launches each workload's kernels three times in turn).
   python -m paper_2308_16877_amd.profiling kernels <kernel_stats.csv> <name-substring> <out.txt> "<title>" "<command>"
+  python -m paper_2308_16877_amd.profiling stall <sq counter_collection.csv> <kernel-name-substring> <workload> \
+        <out.json> "<command>" [a:b]
 
 The traffic summary scales each kernel's FETCH_SIZE and WRITE_SIZE (KiB per
 dispatch) by what the same counter reports for the plain copy probe of a
@@ -195,6 +197,33 @@ def valu_summary(sq_csv, kernel_sub, workload, items, out_json, command, dispatc
     return out
 
 
+def stall_summary(sq_csv, kernel_sub, workload, out_json, command, dispatches=None):
+    """Where a kernel's waves spend their time, from one SQ counter pass:
+    SQ_WAVE_CYCLES (wave-cycles resident) split into SQ_ACTIVE_INST_ANY
+    (working on an instruction), SQ_WAIT_INST_ANY (an instruction ready but
+    not issued: the issue ports or the execution units are busy with other
+    waves' work) and SQ_WAIT_ANY (waiting on a counter: memory, LDS or
+    scalar loads in flight); SQ_ACTIVE_INST_VALU against SQ_BUSY_CYCLES
+    gives the vector units' share."""
+    rows = _dispatch_slice([r for r in csv.DictReader(open(sq_csv)) if _kernel_match(r["Kernel_Name"], kernel_sub)],
+                           dispatches)
+    if not rows:
+        raise SystemExit("no rows for %s in %s" % (kernel_sub, sq_csv))
+    per = {}
+    for r in rows:
+        per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    avg = {c: sum(v) / len(v) for c, v in per.items()}
+    wc = avg["SQ_WAVE_CYCLES"]
+    out = {"kernel": kernel_sub, "workload": workload, "kernel_source_sha": kernel_source_sha(kernel_sub),
+           "counters_per_dispatch": avg,
+           "frac_of_wave_cycles": {"active_inst_any": avg["SQ_ACTIVE_INST_ANY"] / wc,
+                                   "wait_inst_any (ready, not issued)": avg["SQ_WAIT_INST_ANY"] / wc,
+                                   "wait_any (waiting on a counter)": avg["SQ_WAIT_ANY"] / wc},
+           "command": command, "dispatches": dispatches or "all"}
+    json.dump(out, open(out_json, "w"), indent=1)
+    return out
+
+
 def kernels_summary(stats_csv, sub, out_txt, title, command):
     """Per-kernel rocprofv3 statistics of the hpac kernels whose name contains sub."""
     stats = list(csv.DictReader(open(stats_csv)))
@@ -216,6 +245,8 @@ if __name__ == "__main__":
         print(json.dumps(traffic_summary(*sys.argv[2:10]), indent=1))
     elif sys.argv[1] == "valu":
         print(json.dumps(valu_summary(*sys.argv[2:9]), indent=1))
+    elif sys.argv[1] == "stall":
+        print(json.dumps(stall_summary(*sys.argv[2:8]), indent=1))
     elif sys.argv[1] == "kernels":
         kernels_summary(*sys.argv[2:7])
     else:
