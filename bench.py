@@ -865,6 +865,11 @@ def leg_summary(legs):
     if h:
         s["taf_level_speedups"] = {lv: r["speedup_vs_exact"] for lv, r in h["taf"]["levels_at_ipt16"].items()}
         s["iact_level_speedups"] = {lv: r["speedup_vs_exact"] for lv, r in h["iact"]["levels_at_ipt16"].items()}
+        # the parallelism-against-approximation study: speedup and approximated
+        # fraction per items per lane, wave level
+        s["items_per_lane_study"] = {t: {ipt: [r["speedup_vs_exact"], r["approx_frac"]]
+                                         for ipt, r in h[t]["items_per_lane_at_wave_level"].items()}
+                                     for t in ("taf", "iact")}
     bo = legs.get("binomial_options")
     if bo:
         u = bo["variants"]["unit_periodic"]

@@ -224,8 +224,11 @@ hpac_status hpac_bs_vjp_ref(int64_t n, const void *const *in, const int32_t *sou
  * (row = output unit), kept in FP32; the kernels use the weights rounded to
  * BF16 (nearest, ties to even) and the biases in FP32.
  * Normalisation (host values): the network sees xh_j = (x_j - in_center[j])
- * * in_scale[j] and its outputs yh map back to y_o = yh_o * out_scale[o] +
- * out_mean[o].
+ * * in_scale[j]; its outputs yh map back to v_o = yh_o * out_scale[o] +
+ * out_mean[o], and the result is y_o = v_o when out_shift[o] = 0, or
+ * y_o = exp(v_o) - out_shift[o] when out_shift[o] > 0: the network then
+ * models log(y_o + out_shift[o]), whose errors are relative to y_o +
+ * out_shift[o] (prices near zero keep small absolute errors).
  * ------------------------------------------------------------------------ */
 #define HPAC_MLP_NUM_PARAMS 4674
 typedef struct hpac_mlp_norm {
@@ -233,6 +236,7 @@ typedef struct hpac_mlp_norm {
   float in_scale[5];
   float out_mean[2];
   float out_scale[2];
+  float out_shift[2]; /* >= 0, finite */
 } hpac_mlp_norm;
 
 /* Surrogate inference over io->n items (region HPAC_REGION_BS_PRICE, FP32
@@ -247,7 +251,9 @@ hpac_status hpac_surrogate(const hpac_region_io *io, const float *params, const 
                            const float *box_lo, const float *box_hi, int32_t *queue, int32_t *queue_count);
 
 /* Training step, part 1: the gradient of L = 1/(2 N) sum_i sum_o
- * (yh_o(x_i) - (t_o,i - out_mean[o]) / out_scale[o])^2 over the `batch` items
+ * (yh_o(x_i) - (g_o(t_o,i) - out_mean[o]) / out_scale[o])^2 over the `batch`
+ * items, g_o(t) = t, or log(t + out_shift[o]) when out_shift[o] > 0 (targets
+ * t are region outputs, transformed by the kernel)
  * (columns x[5], targets t[2], device) with respect to every parameter, with
  * FP32 activations and BF16-rounded weights (the rounding is passed through
  * as the identity), N = loss_count.  Writes one partial gradient per 64 items:

@@ -76,9 +76,9 @@ def _load():
     lib.or_mlp_gelu.restype = f64
     lib.or_mlp_gelu.argtypes = [f64]
     lib.or_mlp_forward.restype = None
-    lib.or_mlp_forward.argtypes = [i64, P, P, P, P, P, P, i32, i32, P]
+    lib.or_mlp_forward.argtypes = [i64, P, P, P, P, P, P, P, i32, i32, P]
     lib.or_mlp_loss_grad.restype = f64
-    lib.or_mlp_loss_grad.argtypes = [i64, P, P, P, P, P, P, P, i32, P]
+    lib.or_mlp_loss_grad.argtypes = [i64, P, P, P, P, P, P, P, P, i32, P]
     lib.or_binomial.restype = None
     lib.or_binomial.argtypes = [i64, P, P, P, P, P, i32, i32, P, P, P]
     lib.hy_init.restype = ctypes.c_int
@@ -267,7 +267,9 @@ def bf16(v):
 
 
 def _norm_arrays(norm):
-    return [np.ascontiguousarray(norm[k], np.float64) for k in ("in_center", "in_scale", "out_mean", "out_scale")]
+    """in_center, in_scale, out_mean, out_scale and out_shift (zeros when absent)."""
+    arrs = [np.ascontiguousarray(norm[k], np.float64) for k in ("in_center", "in_scale", "out_mean", "out_scale")]
+    return arrs + [np.ascontiguousarray(norm.get("out_shift", np.zeros(2)), np.float64)]
 
 
 def mlp_forward(x, params, norm, round_act=True, act=True):
@@ -277,10 +279,10 @@ def mlp_forward(x, params, norm, round_act=True, act=True):
     n = x[0].size
     w = np.ascontiguousarray(params, np.float64)
     assert w.size == mlp_num_params()
-    c, s, mu, sc = _norm_arrays(norm)
+    c, s, mu, sc, sh = _norm_arrays(norm)
     y = np.empty((2, n), np.float64)
-    _load().or_mlp_forward(n, _cols(x), _ptr(w), _ptr(c), _ptr(s), _ptr(mu), _ptr(sc), int(round_act), int(act),
-                           _cols([y[0], y[1]]))
+    _load().or_mlp_forward(n, _cols(x), _ptr(w), _ptr(c), _ptr(s), _ptr(mu), _ptr(sc), _ptr(sh), int(round_act),
+                           int(act), _cols([y[0], y[1]]))
     return y
 
 
@@ -290,9 +292,9 @@ def mlp_loss_grad(x, targets, params, norm, act=True):
     t = _as_f64_cols(targets)
     n = x[0].size
     w = np.ascontiguousarray(params, np.float64)
-    c, s, mu, sc = _norm_arrays(norm)
+    c, s, mu, sc, sh = _norm_arrays(norm)
     g = np.empty(mlp_num_params(), np.float64)
-    loss = _load().or_mlp_loss_grad(n, _cols(x), _cols(t), _ptr(w), _ptr(c), _ptr(s), _ptr(mu), _ptr(sc),
+    loss = _load().or_mlp_loss_grad(n, _cols(x), _cols(t), _ptr(w), _ptr(c), _ptr(s), _ptr(mu), _ptr(sc), _ptr(sh),
                                     int(act), _ptr(g))
     return loss, g
 

@@ -663,26 +663,33 @@ static void or_mlp_fwd1(const double *w, const double *xin, const double *c, con
   }
 }
 
-/* y (2 columns) = the surrogate's outputs for n items; x is 5 columns. */
+/* y (2 columns) = the surrogate's outputs for n items; x is 5 columns.  The
+ * output map: v = yh sc + mu, and y = v, or exp(v) - sh where sh > 0 (the
+ * network then models log(y + sh)). */
 void or_mlp_forward(int64_t n, const double *const *x, const double *w, const double *c, const double *s,
-                    const double *mu, const double *sc, int32_t round_act, int32_t act, double *const *y) {
+                    const double *mu, const double *sc, const double *sh, int32_t round_act, int32_t act,
+                    double *const *y) {
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     double xin[5];
     or_mlp_act A;
     for (int j = 0; j < 5; ++j) xin[j] = x[j][i];
     or_mlp_fwd1(w, xin, c, s, round_act, act, &A);
-    for (int o = 0; o < 2; ++o) y[o][i] = A.yh[o] * sc[o] + mu[o];
+    for (int o = 0; o < 2; ++o) {
+      const double v = A.yh[o] * sc[o] + mu[o];
+      y[o][i] = sh[o] > 0.0 ? exp(v) - sh[o] : v;
+    }
   }
 }
 
 /* Mean squared error over the n items and 2 outputs in the normalised output
- * space, L = 1/(2n) sum_i sum_o (yh_o - (t_o - mu_o)/sc_o)^2, with FP64
- * activations, and its gradient with respect to every parameter (through
- * the BF16 rounding of the weights as if it were the identity). */
+ * space, L = 1/(2n) sum_i sum_o (yh_o - (g_o(t_o) - mu_o)/sc_o)^2, g_o(t) = t,
+ * or log(t + sh_o) where sh_o > 0, with FP64 activations, and its gradient
+ * with respect to every parameter (through the BF16 rounding of the weights
+ * as if it were the identity). */
 double or_mlp_loss_grad(int64_t n, const double *const *x, const double *const *t, const double *w,
-                        const double *c, const double *s, const double *mu, const double *sc, int32_t act,
-                        double *grad) {
+                        const double *c, const double *s, const double *mu, const double *sc, const double *sh,
+                        int32_t act, double *grad) {
   double loss = 0.0;
   for (int p = 0; p < OR_P; ++p) grad[p] = 0.0;
   for (int64_t i = 0; i < n; ++i) {
@@ -691,7 +698,8 @@ double or_mlp_loss_grad(int64_t n, const double *const *x, const double *const *
     for (int j = 0; j < 5; ++j) xin[j] = x[j][i];
     or_mlp_fwd1(w, xin, c, s, 0, act, &A);
     for (int o = 0; o < 2; ++o) {
-      double e = A.yh[o] - (t[o][i] - mu[o]) / sc[o];
+      const double g = sh[o] > 0.0 ? log(t[o][i] + sh[o]) : t[o][i];
+      double e = A.yh[o] - (g - mu[o]) / sc[o];
       loss += e * e;
       dy[o] = 2.0 * e / (2.0 * (double)n);
       grad[OR_OFF_B3 + o] += dy[o];

@@ -169,7 +169,7 @@ hpac_status hip_status(const char *fn, hipError_t e) {
 
 extern "C" {
 
-int32_t hpac_abi_version(void) { return 2; }
+int32_t hpac_abi_version(void) { return 3; }
 
 const char *hpac_last_error(void) { return g_err; }
 
@@ -298,7 +298,7 @@ hpac_status hpac_bs_adjoint(int64_t n, const void *const *in, const float *grad_
 }
 
 static hpac_status copy_norm(const char *fn, const hpac_mlp_norm *norm, float *c, float *s, float *mu,
-                             float *sc) {
+                             float *sc, float *sh) {
   if (!norm) return fail(HPAC_EINVAL, "%s: norm is NULL", fn);
   for (int j = 0; j < 5; ++j) {
     if (!isfinite(norm->in_center[j]) || !isfinite(norm->in_scale[j]))
@@ -309,8 +309,11 @@ static hpac_status copy_norm(const char *fn, const hpac_mlp_norm *norm, float *c
   for (int o = 0; o < 2; ++o) {
     if (!isfinite(norm->out_mean[o]) || !isfinite(norm->out_scale[o]) || norm->out_scale[o] == 0.0f)
       return fail(HPAC_EINVAL, "%s: output normalisation must be finite with a non-zero scale", fn);
+    if (!isfinite(norm->out_shift[o]) || !(norm->out_shift[o] >= 0.0f))
+      return fail(HPAC_EINVAL, "%s: output shifts must be finite and >= 0", fn);
     mu[o] = norm->out_mean[o];
     sc[o] = norm->out_scale[o];
+    sh[o] = norm->out_shift[o];
   }
   return HPAC_OK;
 }
@@ -327,7 +330,8 @@ hpac_status hpac_surrogate(const hpac_region_io *io, const float *params, const 
   if (io->n > 2147483647) return fail(HPAC_EINVAL, "%s: at most 2^31-1 items per call (int32 queue)", fn);
   if (!box_lo || !box_hi) return fail(HPAC_EINVAL, "%s: NULL box", fn);
   hpac::MlpArgs a = {};
-  if ((s = copy_norm(fn, norm, a.in_center, a.in_scale, a.out_mean, a.out_scale)) != HPAC_OK) return s;
+  s = copy_norm(fn, norm, a.in_center, a.in_scale, a.out_mean, a.out_scale, a.out_shift);
+  if (s != HPAC_OK) return s;
   for (int j = 0; j < 5; ++j) {
     a.box_lo[j] = box_lo[j];
     a.box_hi[j] = box_hi[j];
@@ -355,7 +359,7 @@ hpac_status hpac_mlp_grad(int64_t batch, const float *const *x, const float *con
     return fail(HPAC_EINVAL, "%s: batch = %lld out of range [0, 2^32 - 64]", fn, (long long)batch);
   if (loss_count < 1) return fail(HPAC_EINVAL, "%s: loss_count must be >= 1", fn);
   hpac::MlpGradArgs a = {};
-  hpac_status s = copy_norm(fn, norm, a.in_center, a.in_scale, a.out_mean, a.out_scale);
+  hpac_status s = copy_norm(fn, norm, a.in_center, a.in_scale, a.out_mean, a.out_scale, a.out_shift);
   if (s != HPAC_OK || batch == 0) return s;
   if (!x || !t || !params || !grad_partials || !loss_partials) return fail(HPAC_EINVAL, "%s: NULL pointer", fn);
   for (int j = 0; j < 5; ++j)

@@ -12,6 +12,7 @@ struct MlpArgs {
   float *out[2];
   const float *params;
   float in_center[5], in_scale[5], out_mean[2], out_scale[2];
+  float out_shift[2];  // > 0: outputs are exp(v) - shift (the network models log(y + shift))
   float box_lo[5], box_hi[5];
   int32_t *queue;
   int32_t *queue_count;
@@ -22,6 +23,7 @@ struct MlpGradArgs {
   const float *t[2];
   const float *params;
   float in_center[5], in_scale[5], out_mean[2], out_scale[2];
+  float out_shift[2];  // > 0: targets are taken as log(t + shift)
   float inv_count;  // 1 / number of items the loss averages over
   float *grad_partials;
   float *loss_partials;

@@ -47,6 +47,18 @@ __device__ __forceinline__ float gelu_d(float x) {
 
 __device__ __forceinline__ float round_bf16(float v) { return (float)(__bf16)v; }
 
+// Output o of the network's normalised output yh: the affine map back, then
+// exp(v) - shift where the network models log(y + shift).
+__device__ __forceinline__ float out_map(const MlpArgs &a, int o, float yh) {
+  const float v = __builtin_fmaf(yh, a.out_scale[o], a.out_mean[o]);
+  return a.out_shift[o] > 0.0f ? expf(v) - a.out_shift[o] : v;
+}
+
+// Training target o in the network's output space.
+__device__ __forceinline__ float target_map(const MlpGradArgs &a, int o, float t) {
+  return a.out_shift[o] > 0.0f ? logf(t + a.out_shift[o]) : t;
+}
+
 // ------------------------------------------------------------------ infer
 
 // permuted position of reduction slot (lane group g, slot j) in chunk c:
@@ -176,8 +188,8 @@ __global__ void __launch_bounds__(256) k_mlp_infer(MlpArgs a) {
       D3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W3[1], h2[1], D3, 0, 0, 0);
       // rows 0 and 1 (the two outputs) live in lanes 0..15, slots 0 and 1
       if (g == 0) {
-        ys[w][16 * tn + r][0] = __builtin_fmaf(D3[0], a.out_scale[0], a.out_mean[0]);
-        ys[w][16 * tn + r][1] = __builtin_fmaf(D3[1], a.out_scale[1], a.out_mean[1]);
+        ys[w][16 * tn + r][0] = out_map(a, 0, D3[0]);
+        ys[w][16 * tn + r][1] = out_map(a, 1, D3[1]);
       }
     }
     wave_lds_fence();
@@ -253,8 +265,8 @@ __global__ void __launch_bounds__(64) k_mlp_grad(MlpGradArgs a) {
     yh1 = __builtin_fmaf(W[kOffW3 + kNH + j], h[j], yh1);
   }
   // loss 1/(2N) sum (yh - th)^2 over the N training items and both outputs
-  const float e0 = active ? yh0 - (a.t[0][i] - a.out_mean[0]) / a.out_scale[0] : 0.0f;
-  const float e1 = active ? yh1 - (a.t[1][i] - a.out_mean[1]) / a.out_scale[1] : 0.0f;
+  const float e0 = active ? yh0 - (target_map(a, 0, a.t[0][i]) - a.out_mean[0]) / a.out_scale[0] : 0.0f;
+  const float e1 = active ? yh1 - (target_map(a, 1, a.t[1][i]) - a.out_mean[1]) / a.out_scale[1] : 0.0f;
   const float dy0 = e0 * a.inv_count, dy1 = e1 * a.inv_count;
   dys[t][0] = dy0;
   dys[t][1] = dy1;

@@ -47,15 +47,17 @@ class hpac_region_io(ctypes.Structure):
 
 class hpac_mlp_norm(ctypes.Structure):
     _fields_ = [("in_center", ctypes.c_float * 5), ("in_scale", ctypes.c_float * 5),
-                ("out_mean", ctypes.c_float * 2), ("out_scale", ctypes.c_float * 2)]
+                ("out_mean", ctypes.c_float * 2), ("out_scale", ctypes.c_float * 2),
+                ("out_shift", ctypes.c_float * 2)]
 
 
 MLP_NUM_PARAMS = 4674
 
 
-def make_norm(in_center, in_scale, out_mean, out_scale):
+def make_norm(in_center, in_scale, out_mean, out_scale, out_shift=(0.0, 0.0)):
     return hpac_mlp_norm((ctypes.c_float * 5)(*map(float, in_center)), (ctypes.c_float * 5)(*map(float, in_scale)),
-                         (ctypes.c_float * 2)(*map(float, out_mean)), (ctypes.c_float * 2)(*map(float, out_scale)))
+                         (ctypes.c_float * 2)(*map(float, out_mean)), (ctypes.c_float * 2)(*map(float, out_scale)),
+                         (ctypes.c_float * 2)(*map(float, out_shift)))
 
 
 class HpacError(RuntimeError):

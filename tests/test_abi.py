@@ -24,7 +24,7 @@ def test_library_exports_every_declared_symbol():
     lib = hpac.lib()
     for name in names:
         assert hasattr(lib, name), name
-    assert lib.hpac_abi_version() == 2
+    assert lib.hpac_abi_version() == 3
 
 
 def test_lane_mapping():
@@ -273,6 +273,11 @@ def test_grids_beyond_32_bit_lane_counts_are_rejected():
     # training batches: one lane per sample
     nm = hpac.make_norm([0] * 5, [1] * 5, [0, 0], [1, 1])
     expect(E, hpac.hpac_mlp_grad, [FAKE] * 5, [FAKE] * 2, FAKE, nm, 1, FAKE, FAKE, n=2**32)
+    # output shifts (log outputs) must be finite and >= 0
+    for bad in ((-0.01, 0.0), (0.0, float("nan")), (float("inf"), 0.0)):
+        nm = hpac.make_norm([0] * 5, [1] * 5, [0, 0], [1, 1], bad)
+        msg = expect(E, hpac.hpac_mlp_grad, [FAKE] * 5, [FAKE] * 2, FAKE, nm, 1, FAKE, FAKE, n=64)
+        assert "shift" in msg
 
 
 def test_short_or_mistyped_buffers_are_rejected_by_the_binding():

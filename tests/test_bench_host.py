@@ -55,7 +55,9 @@ def _fake_legs():
                                                                      "iact_gradient_mape_vs_exact": 0.001}},
         "precision": {"fp32_body_fp32_columns": {"speedup_vs_fp32": 1.0, "mape_vs_fp32": 0.0},
                       "fp32_body_fp16_columns": {"speedup_vs_fp32": 1.4, "mape_vs_fp32": 0.0006}},
-        "hierarchy_and_items_per_lane": {"taf": {"levels_at_ipt16": lvl}, "iact": {"levels_at_ipt16": lvl}},
+        "hierarchy_and_items_per_lane": {t: {"levels_at_ipt16": lvl, "items_per_lane_at_wave_level": {
+            str(2 ** k): {"speedup_vs_exact": 1.0123456, "approx_frac": 0.7483123, "mape": 0.002} for k in range(7)}}
+            for t in ("taf", "iact")},
         "binomial_options": {"variants": {"unit_periodic": bo}},
         "surrogate": {"speedup_vs_exact": 0.2, "mape_vs_exact": 0.004, "rel_l2_vs_exact": 0.001,
                       "items_per_s": 3e10},

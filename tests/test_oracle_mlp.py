@@ -71,6 +71,28 @@ def test_zero_weights_output_the_bias():
     assert np.allclose(y[0], 0.5 * 4.0 + 3.0) and np.allclose(y[1], -0.25 * 25.0 + 40.0)
 
 
+def test_zero_weights_with_log_outputs():
+    """With out_shift > 0 a zero-weight network outputs exp(bias * scale +
+    mean) - shift, and the loss of constant targets t is zero exactly when the
+    bias is (log(t + shift) - mean) / scale: the forward map and the
+    training target's transform are inverse to each other."""
+    x = inputs.uniform_box(50, seed=11)
+    n = dict(norm(), out_shift=np.array([0.01, 0.5]))
+    t = np.array([1e-6, 12.5])  # a near-worthless call and an ordinary put
+    w = np.zeros(P)
+    w[4672:] = (np.log(t + n["out_shift"]) - n["out_mean"]) / n["out_scale"]
+    y = oracle.mlp_forward(x, w, n, round_act=False)
+    assert np.allclose(y, t[:, None], rtol=1e-12, atol=1e-15)
+    loss, g = oracle.mlp_loss_grad(x, np.repeat(t[:, None], 50, axis=1), w, n)
+    assert loss < 1e-28 and np.max(np.abs(g)) < 1e-12
+    # without the shift the same bias is far from the targets
+    loss0, _ = oracle.mlp_loss_grad(x, np.repeat(t[:, None], 50, axis=1), w, norm())
+    assert loss0 > 0.1
+    w[4672:] = [0.5, -0.25]
+    y = oracle.mlp_forward(x, w, n, round_act=False)
+    assert np.allclose(y[0], np.exp(0.5 * 4.0 + 3.0) - 0.01) and np.allclose(y[1], np.exp(-0.25 * 25.0 + 40.0) - 0.5)
+
+
 def test_identity_activation_is_plain_matrix_products():
     w = random_params(5)
     x = inputs.uniform_box(300, seed=4)
@@ -83,14 +105,18 @@ def test_identity_activation_is_plain_matrix_products():
     assert np.allclose(y, ref, rtol=1e-12, atol=1e-12)
 
 
-@pytest.mark.parametrize("act", [True, False])
-def test_loss_gradient_matches_finite_differences(act):
+@pytest.mark.parametrize("act,shift", [(True, 0.0), (False, 0.0), (True, 0.01)])
+def test_loss_gradient_matches_finite_differences(act, shift):
     # perturb biases and a sample of weights whose BF16 rounding is the
     # identity for the step used (exact BF16 values with spare bits)
     w = oracle.bf16(random_params(7, 0.2))
     x = inputs.uniform_box(64, seed=8)
     C, Pp, _, _ = oracle.bs_price(*x)
     n = norm()
+    if shift:
+        # log targets: their own mean and deviation
+        lt = np.log(np.stack([C, Pp]) + shift)
+        n = dict(n, out_mean=lt.mean(axis=1), out_scale=lt.std(axis=1), out_shift=np.array([shift, shift]))
     loss, g = oracle.mlp_loss_grad(x, np.stack([C, Pp]), w, n, act=act)
     rng = np.random.default_rng(9)
     idx = list(range(320, 384)) + list(range(4480, 4544)) + [4672, 4673]
