@@ -179,9 +179,23 @@ hpac_status hpac_iact(const hpac_region_io *io, int32_t table_size, float thresh
  *   as var == 0 ? threshold > 0 : var < threshold^2 * mu^2.  A passing group
  *   approximates its next prediction_size steps: each active lane writes its
  *   last accurate output and reads no input.  The window slides over
- *   accurate steps only and is never reset within a launch. */
+ *   accurate steps only and is never reset within a launch.
+ * persistent_state: NULL keeps the state within the launch (the paper's
+ *   kernel-scoped state, section 3.1.1).  Otherwise a device buffer of
+ *   hpac_taf_state_bytes(region, n, items_per_lane, history_size) bytes,
+ *   4-byte aligned, owned by the caller and zeroed before the first launch:
+ *   each lane's window and fill and its group's remaining approximate steps
+ *   are read from it at the start and written back at the end, so that a
+ *   sequence of launches of the same shape (region, n, items_per_lane,
+ *   block_size, level, history_size) continues each lane's sequence of
+ *   steps -- output memoization across calls, as across the timesteps of a
+ *   simulation.  Launches that share a state must not overlap. */
 hpac_status hpac_taf(const hpac_region_io *io, int32_t history_size, int32_t prediction_size,
-                     float rsd_threshold, int32_t level);
+                     float rsd_threshold, int32_t level, void *persistent_state);
+/* Bytes of a persistent TAF state for that launch shape (the window of
+ * history_size outputs and two int32 per logical lane); -1 if an argument
+ * is out of range. */
+int64_t hpac_taf_state_bytes(int32_t region, int64_t n, int32_t items_per_lane, int32_t history_size);
 
 /* Herded loop perforation (sections 2.3, 3.1.5, 3.3): every lane drops the
  * same steps, so control flow stays uniform across each wave.

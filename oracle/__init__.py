@@ -64,7 +64,7 @@ def _load():
     lib.or_adam.restype = None
     lib.or_adam.argtypes = [i64, i64, P, P, P, P, f64, f64, f64, f64, i32]
     lib.or_taf.restype = ctypes.c_int
-    lib.or_taf.argtypes = [i64, i32, i32, i32, P, P, i32, i32, f32, f64, P, P, P, P, P, P, P]
+    lib.or_taf.argtypes = [i64, i32, i32, i32, P, P, i32, i32, f32, f64, P, P, P, P, P, P, P, P]
     lib.or_perfo.restype = ctypes.c_int
     lib.or_perfo.argtypes = [i64, i32, i32, P, P, i32, i32, i32, P, P, P, P]
     lib.or_mape.restype = None
@@ -201,8 +201,23 @@ def adam(partials, w, m, v, lr, beta1, beta2, eps, step):
     return w, m, v
 
 
-def taf(y, s, ipt, history_size, prediction_size, threshold, band=0.0, group=GROUP_WAVE, out_init=None):
-    """TAF engine over region values y (n_out, n)."""
+class _TafState(ctypes.Structure):
+    _fields_ = [("win", ctypes.c_void_p), ("last", ctypes.c_void_p), ("lasts", ctypes.c_void_p),
+                ("fill", ctypes.c_void_p), ("rho", ctypes.c_void_p)]
+
+
+def taf_state(n, ipt, history_size, n_out=2):
+    """A fresh state for TAF launches of this shape carrying windows and
+    countdowns across launches (numpy arrays, updated in place by taf())."""
+    L = num_lanes(n, ipt)
+    return dict(win=np.zeros(L * n_out * history_size), last=np.zeros(L * n_out), lasts=np.zeros(L * n_out),
+                fill=np.zeros(L, np.int32), rho=np.zeros(L, np.int32), shape=(n, ipt, history_size, n_out))
+
+
+def taf(y, s, ipt, history_size, prediction_size, threshold, band=0.0, group=GROUP_WAVE, out_init=None,
+        state=None):
+    """TAF engine over region values y (n_out, n); with state (taf_state),
+    the launch starts from it and leaves its end state in it."""
     y = _as_f64_cols(y)
     s = _as_f64_cols(s) if s is not None else [np.zeros_like(c) for c in y]
     n = y[0].size
@@ -213,9 +228,14 @@ def taf(y, s, ipt, history_size, prediction_size, threshold, band=0.0, group=GRO
     fragile = np.empty(W * ipt, np.uint8)
     napprox = np.empty(W * ipt, np.int16)
     evals = ctypes.c_int64(0)
+    st = None
+    if state is not None:
+        assert state["shape"] == (n, ipt, history_size, len(y)), "state of another launch shape"
+        st = _TafState(*[_ptr(state[k]) for k in ("win", "last", "lasts", "fill", "rho")])
     rc = _load().or_taf(n, ipt, group, len(y), _cols(y), _cols(s), history_size, prediction_size,
                         np.float32(threshold), float(band), _cols(list(out)), _cols(list(osc)),
-                        _ptr(dec), _ptr(votes), _ptr(fragile), _ptr(napprox), ctypes.byref(evals))
+                        _ptr(dec), _ptr(votes), _ptr(fragile), _ptr(napprox), ctypes.byref(evals),
+                        ctypes.byref(st) if st is not None else None)
     if rc != 0:
         raise ValueError("or_taf rejected its arguments")
     return dict(out=out, scale=osc, dec=dec, votes=votes, fragile=fragile,

@@ -366,6 +366,11 @@ int or_iact(int64_t n, int32_t ipt, int32_t group, int32_t n_in,
 /* returns its last accurately computed output without evaluating the       */
 /* region.  The window is not reset by a stable regime.                     */
 /* `band` marks lanes whose RSD lies within band*theta of theta.            */
+/* State across launches (st non-NULL): each lane's window, fill, last       */
+/* output (and its tolerance scale) and its group's remaining approximate    */
+/* steps are read from st at the start and written back at the end, so a    */
+/* launch continues every lane's sequence of steps where the previous        */
+/* launch of the same shape left it (a state of zeros is a fresh start).     */
 /* ------------------------------------------------------------------------ */
 
 static double or_rsd(const double *w, int h) {
@@ -383,11 +388,20 @@ static double or_rsd(const double *w, int h) {
 
 #define OR_MAX_H 64
 
+/* A launch's TAF state, per logical lane l of L (the oracle's own layout):
+ * win[(l * n_out + o) * h + q] (q = 0 the oldest of the fill entries),
+ * last and lasts [l * n_out + o], fill[l], rho[l] (the group's countdown,
+ * the same for every lane of a group). */
+typedef struct {
+  double *win, *last, *lasts;
+  int32_t *fill, *rho;
+} or_taf_state;
+
 int or_taf(int64_t n, int32_t ipt, int32_t group, int32_t n_out,
            const double *const *ysrc, const double *const *ssrc, int32_t hsize,
            int32_t psize, float theta, double band, double *const *out,
            double *const *oscale, int8_t *dec, int16_t *votes, uint8_t *fragile,
-           int16_t *napprox, int64_t *n_evals) {
+           int16_t *napprox, int64_t *n_evals, const or_taf_state *st) {
   if (n_out < 1 || n_out > OR_MAX_OUT || hsize < 1 || hsize > OR_MAX_H || psize < 1) return -1;
   if (group < 1 || (group != 1 && group % OR_WAVE)) return -1;
   int64_t L = or_num_lanes(n, ipt);
@@ -414,6 +428,19 @@ int or_taf(int64_t n, int32_t ipt, int32_t group, int32_t n_out,
     int *near = calloc(nl, sizeof(int));
     int *took = calloc(nl, sizeof(int));
     int *voted = calloc(nl, sizeof(int));
+    if (st) {
+      for (int64_t j = 0; j < nl; ++j) {
+        const int64_t l = l0 + j;
+        for (int o = 0; o < n_out; ++o) {
+          for (int q = 0; q < hsize; ++q)
+            win[((size_t)j * n_out + o) * hsize + q] = st->win[((size_t)l * n_out + o) * hsize + q];
+          last[j * n_out + o] = st->last[l * n_out + o];
+          lasts[j * n_out + o] = st->lasts[l * n_out + o];
+        }
+        fill[j] = st->fill[l];
+      }
+      for (int64_t gi = 0; gi < ngroups; ++gi) rho[gi] = st->rho[l0 + gi * group];
+    }
 
     for (int32_t k = 0; k < ipt; ++k) {
       for (int64_t gi = 0; gi < ngroups; ++gi) {
@@ -499,6 +526,19 @@ int or_taf(int64_t n, int32_t ipt, int32_t group, int32_t n_out,
           for (int64_t j = wl * OR_WAVE; j < (wl + 1) * OR_WAVE; ++j) { nv += voted[j]; wy += voted[j] && crit[j]; }
           votes[w * ipt + k] = nv ? (int16_t)wy : -1;
         }
+      }
+    }
+    if (st) {
+      for (int64_t j = 0; j < nl; ++j) {
+        const int64_t l = l0 + j;
+        for (int o = 0; o < n_out; ++o) {
+          for (int q = 0; q < hsize; ++q)
+            st->win[((size_t)l * n_out + o) * hsize + q] = win[((size_t)j * n_out + o) * hsize + q];
+          st->last[l * n_out + o] = last[j * n_out + o];
+          st->lasts[l * n_out + o] = lasts[j * n_out + o];
+        }
+        st->fill[l] = fill[j];
+        st->rho[l] = rho[j / group];
       }
     }
     free(win); free(last); free(lasts); free(fill); free(rho);

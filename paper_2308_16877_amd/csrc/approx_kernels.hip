@@ -498,8 +498,39 @@ __device__ __forceinline__ bool rsd_below(const float (&w)[H][NO], double th2, b
   return ok;
 }
 
+// TAF state carried between launches (caller-owned, zeroed before the
+// first one), per logical lane l of the launch's L lanes: the window, word
+// (q * NO + o) * L + l (q = H - 1 the newest output), then the window's fill
+// and the group's remaining approximate steps as int32[L] each.  A launch
+// with a state starts from it and leaves its own end state there, so lane l
+// continues its sequence of steps across launches of the same shape.
+template <int H, int NO>
+struct TafState {
+  float *base;
+  int64_t L;
+  __device__ __forceinline__ float *word(int q, int o) const { return base + ((int64_t)q * NO + o) * L; }
+  __device__ __forceinline__ int32_t *fill() const { return (int32_t *)(base + (int64_t)H * NO * L); }
+  __device__ __forceinline__ int32_t *rho() const { return fill() + L; }
+  __device__ __forceinline__ void load(int64_t l, float (&w)[H][NO], int &f, int &r) const {
+#pragma unroll
+    for (int q = 0; q < H; ++q)
+#pragma unroll
+      for (int o = 0; o < NO; ++o) w[q][o] = word(q, o)[l];
+    f = fill()[l];
+    r = rho()[l];
+  }
+  __device__ __forceinline__ void store(int64_t l, const float (&w)[H][NO], int f, int r) const {
+#pragma unroll
+    for (int q = 0; q < H; ++q)
+#pragma unroll
+      for (int o = 0; o < NO; ++o) word(q, o)[l] = w[q][o];
+    fill()[l] = f;
+    rho()[l] = r;
+  }
+};
+
 template <class R, int LEVEL, int H>
-__global__ void __launch_bounds__(256) k_taf(KArgs a, int psize, float theta) {
+__global__ void __launch_bounds__(256) k_taf(KArgs a, int psize, float theta, float *state) {
   __shared__ int tally_mem[6];
   __shared__ unsigned long long sums[4];
   const LaneGeom g;
@@ -517,6 +548,8 @@ __global__ void __launch_bounds__(256) k_taf(KArgs a, int psize, float theta) {
     for (int o = 0; o < R::kOut; ++o) win[q][o] = 0.0f;
   int fill = 0;
   int rho = 0;  // remaining approximate steps (uniform per group)
+  const TafState<H, R::kOut> ts{state, a.L};
+  if (state && g.l < a.L) ts.load(g.l, win, fill, rho);
   bool prev_stable = false;
   WaveStats st;
   float xa[R::kIn], xb[R::kIn];
@@ -587,6 +620,7 @@ __global__ void __launch_bounds__(256) k_taf(KArgs a, int psize, float theta) {
     }
     return true;
   });
+  if (state && g.l < a.L) ts.store(g.l, win, fill, rho);
   sink.end(st);
 }
 
@@ -599,7 +633,7 @@ __global__ void __launch_bounds__(256) k_taf(KArgs a, int psize, float theta) {
 // (the vote is then likely to fail again); a pass wastes that load once.
 // Same decisions as k_taf at wave level.
 template <class R, int H>
-__global__ void __launch_bounds__(256) k_taf_wave(KArgs a, int psize, float theta) {
+__global__ void __launch_bounds__(256) k_taf_wave(KArgs a, int psize, float theta, float *state) {
   __shared__ unsigned long long sums[4];
   const LaneGeom g;
   const int lane = lane_id();
@@ -615,11 +649,27 @@ __global__ void __launch_bounds__(256) k_taf_wave(KArgs a, int psize, float thet
   int fill = 0;
   bool prev_pass = false;
   WaveStats st;
+  // with a state: the window, and the approximate steps still owed to the
+  // previous launch's last passing vote (the same for every lane of a wave)
+  const TafState<H, R::kOut> ts{state, a.L};
+  int owed = 0;
+  if (state && g.l < a.L) ts.load(g.l, win, fill, owed);
+  owed = __builtin_amdgcn_readfirstlane(owed);
+  int k = 0;
+  for (; k < owed && k < a.ipt && g.wave_has(a, k); ++k) {
+    const bool act = g.active(a, k);
+    if (act) store_outputs<R>(a, g.item(a, k), win[H - 1]);
+    if (a.trace || a.counters) {
+      const int nact = popc(ballot(act));
+      st.add(nact, nact, true);
+      if (a.trace && lane == 0) a.trace[g.trace_index(a, k)] = trace_word(0, nact, -1, true, false);
+    }
+  }
+  int left = owed - k > 0 ? owed - k : 0;  // still owed when the launch ends
   float x[R::kIn], xn[R::kIn];
 #pragma unroll
   for (int j = 0; j < R::kIn; ++j) xn[j] = 0.0f;
-  load_first<R>(a, g, true, xn);
-  int k = 0;
+  if (k < a.ipt && g.active(a, k)) load_inputs<R>(a, g.item(a, k), xn);
   while (k < a.ipt && g.wave_has(a, k)) {
 #pragma unroll
     for (int j = 0; j < R::kIn; ++j) x[j] = xn[j];
@@ -654,8 +704,10 @@ __global__ void __launch_bounds__(256) k_taf_wave(KArgs a, int psize, float thet
       if (a.trace && lane == 0)
         a.trace[g.trace_index(a, k)] = trace_word(any_vote ? popc(vmask) : 0, 0, -1, false, any_vote);
     }
+    left = 0;
     if (pass) {
-      for (int kk = k + 1; kk < next && kk < a.ipt && g.wave_has(a, kk); ++kk) {
+      int kk = k + 1;
+      for (; kk < next && kk < a.ipt && g.wave_has(a, kk); ++kk) {
         const bool act = g.active(a, kk);
         if (act) store_outputs<R>(a, g.item(a, kk), win[H - 1]);
         if (a.trace || a.counters) {
@@ -664,10 +716,12 @@ __global__ void __launch_bounds__(256) k_taf_wave(KArgs a, int psize, float thet
           if (a.trace && lane == 0) a.trace[g.trace_index(a, kk)] = trace_word(0, nact, -1, true, false);
         }
       }
+      left = next - kk;
     }
     prev_pass = pass;
     k = next;
   }
+  if (state && g.l < a.L) ts.store(g.l, win, fill, left);
   sink.end(st);
 }
 
@@ -864,24 +918,24 @@ hipError_t launch_iact(const LaunchCfg &c, const KArgs &a, int level, int table_
 }
 
 template <class R, int LEVEL, int H>
-static void taf_go(const LaunchCfg &c, const KArgs &a, int p, float thr) {
+static void taf_go(const LaunchCfg &c, const KArgs &a, int p, float thr, float *st) {
   if (LEVEL == kWaveLvl)
-    hipLaunchKernelGGL((k_taf_wave<R, H>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a, p, thr);
+    hipLaunchKernelGGL((k_taf_wave<R, H>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a, p, thr, st);
   else
-    hipLaunchKernelGGL((k_taf<R, LEVEL, H>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a, p, thr);
+    hipLaunchKernelGGL((k_taf<R, LEVEL, H>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a, p, thr, st);
 }
 
 template <class R, int LEVEL>
-static void taf_h(const LaunchCfg &c, const KArgs &a, int h, int p, float thr) {
+static void taf_h(const LaunchCfg &c, const KArgs &a, int h, int p, float thr, float *st) {
   switch (h) {
-    case 1: taf_go<R, LEVEL, 1>(c, a, p, thr); break;
-    case 2: taf_go<R, LEVEL, 2>(c, a, p, thr); break;
-    case 3: taf_go<R, LEVEL, 3>(c, a, p, thr); break;
-    case 4: taf_go<R, LEVEL, 4>(c, a, p, thr); break;
-    case 5: taf_go<R, LEVEL, 5>(c, a, p, thr); break;
-    case 6: taf_go<R, LEVEL, 6>(c, a, p, thr); break;
-    case 7: taf_go<R, LEVEL, 7>(c, a, p, thr); break;
-    default: taf_go<R, LEVEL, 8>(c, a, p, thr); break;
+    case 1: taf_go<R, LEVEL, 1>(c, a, p, thr, st); break;
+    case 2: taf_go<R, LEVEL, 2>(c, a, p, thr, st); break;
+    case 3: taf_go<R, LEVEL, 3>(c, a, p, thr, st); break;
+    case 4: taf_go<R, LEVEL, 4>(c, a, p, thr, st); break;
+    case 5: taf_go<R, LEVEL, 5>(c, a, p, thr, st); break;
+    case 6: taf_go<R, LEVEL, 6>(c, a, p, thr, st); break;
+    case 7: taf_go<R, LEVEL, 7>(c, a, p, thr, st); break;
+    default: taf_go<R, LEVEL, 8>(c, a, p, thr, st); break;
   }
 }
 
@@ -890,20 +944,26 @@ struct TafL {
   const KArgs &a;
   int level, h, p;
   float thr;
+  float *st;
   template <class R>
   hipError_t go() const {
     switch (level) {
-      case kThread: taf_h<R, kThread>(c, a, h, p, thr); break;
-      case kWaveLvl: taf_h<R, kWaveLvl>(c, a, h, p, thr); break;
-      default: taf_h<R, kBlock>(c, a, h, p, thr); break;
+      case kThread: taf_h<R, kThread>(c, a, h, p, thr, st); break;
+      case kWaveLvl: taf_h<R, kWaveLvl>(c, a, h, p, thr, st); break;
+      default: taf_h<R, kBlock>(c, a, h, p, thr, st); break;
     }
     return hipGetLastError();
   }
 };
 
 hipError_t launch_taf(const LaunchCfg &c, const KArgs &a, int level, int history_size, int prediction_size,
-                      float threshold) {
-  return with_region(c.region, c.dtype, TafL{c, a, level, history_size, prediction_size, threshold});
+                      float threshold, void *state) {
+  return with_region(c.region, c.dtype,
+                     TafL{c, a, level, history_size, prediction_size, threshold, static_cast<float *>(state)});
+}
+
+int64_t taf_state_bytes(int n_out, int64_t lanes, int history_size) {
+  return lanes * ((int64_t)history_size * n_out + 2) * 4;
 }
 
 hipError_t launch_copy(const void *src, void *dst, int64_t bytes, hipStream_t stream) {

@@ -173,6 +173,14 @@ int32_t hpac_abi_version(void) { return 3; }
 
 const char *hpac_last_error(void) { return g_err; }
 
+int64_t hpac_taf_state_bytes(int32_t region, int64_t n, int32_t items_per_lane, int32_t history_size) {
+  RegionShape rs;
+  if (!region_shape(region, &rs) || region == HPAC_REGION_BS_PRICE_REF || n < 0 || n > kMaxItems ||
+      items_per_lane < 1 || items_per_lane > kMaxIpt || history_size < 1 || history_size > 8)
+    return -1;
+  return hpac::taf_state_bytes(rs.n_out, num_lanes(n, items_per_lane), history_size);
+}
+
 int64_t hpac_num_lanes(int64_t n, int32_t items_per_lane) {
   if (n < 0 || n > kMaxItems || items_per_lane < 1 || items_per_lane > kMaxIpt) return -1;
   return num_lanes(n, items_per_lane);
@@ -212,7 +220,7 @@ hpac_status hpac_iact(const hpac_region_io *io, int32_t table_size, float thresh
 }
 
 hpac_status hpac_taf(const hpac_region_io *io, int32_t history_size, int32_t prediction_size, float rsd_threshold,
-                     int32_t level) {
+                     int32_t level, void *persistent_state) {
   const char *fn = "hpac_taf";
   hpac::KArgs a;
   hpac::LaunchCfg c;
@@ -225,8 +233,10 @@ hpac_status hpac_taf(const hpac_region_io *io, int32_t history_size, int32_t pre
   if (prediction_size < 1) return fail(HPAC_EINVAL, "%s: prediction_size = %d must be >= 1", fn, prediction_size);
   if ((s = check_threshold(fn, rsd_threshold)) != HPAC_OK) return s;
   if ((s = check_level(fn, level)) != HPAC_OK) return s;
+  if ((uintptr_t)persistent_state % 4) return fail(HPAC_EINVAL, "%s: persistent_state is misaligned", fn);
   if (a.n == 0) return HPAC_OK;
-  return hip_status(fn, hpac::launch_taf(c, a, level, history_size, prediction_size, rsd_threshold));
+  return hip_status(fn, hpac::launch_taf(c, a, level, history_size, prediction_size, rsd_threshold,
+                                         persistent_state));
 }
 
 hpac_status hpac_perfo(const hpac_region_io *io, int32_t kind, int32_t param, int32_t offset) {

@@ -32,7 +32,9 @@ hipError_t launch_exact(const LaunchCfg &c, const KArgs &a);
 hipError_t launch_iact(const LaunchCfg &c, const KArgs &a, int level, int table_size, float threshold,
                        int tables_per_wave);
 hipError_t launch_taf(const LaunchCfg &c, const KArgs &a, int level, int history_size, int prediction_size,
-                      float threshold);
+                      float threshold, void *state);
+// Bytes of a persistent TAF state: the window and two int32 per lane.
+int64_t taf_state_bytes(int n_out, int64_t lanes, int history_size);
 hipError_t launch_perfo(const LaunchCfg &c, const KArgs &a, int kind, int param, int offset);
 hipError_t launch_copy(const void *src, void *dst, int64_t bytes, hipStream_t stream);
 hipError_t launch_probe_valu(float *out, int workgroups, int iters, bool scalar_operand, hipStream_t stream);

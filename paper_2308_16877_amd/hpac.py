@@ -101,7 +101,9 @@ def lib():
     i32, i64, f32, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_void_p
     L.hpac_exact.argtypes = [IO]
     L.hpac_iact.argtypes = [IO, i32, f32, i32, i32]
-    L.hpac_taf.argtypes = [IO, i32, i32, f32, i32]
+    L.hpac_taf.argtypes = [IO, i32, i32, f32, i32, vp]
+    L.hpac_taf_state_bytes.argtypes = [i32, i64, i32, i32]
+    L.hpac_taf_state_bytes.restype = i64
     L.hpac_perfo.argtypes = [IO, i32, i32, i32]
     L.hpac_probe_copy.argtypes = [vp, vp, i64, vp]
     L.hpac_probe_valu.argtypes = [vp, i32, i32, i32, vp]
@@ -277,9 +279,22 @@ def hpac_iact(inputs, outputs, table_size, threshold, tables_per_wave=1, level="
     _call("hpac_iact", lib().hpac_iact(ctypes.byref(io), table_size, threshold, tables_per_wave, _level(level)))
 
 
-def hpac_taf(inputs, outputs, history_size, prediction_size, rsd_threshold, level="wave", **kw):
+def hpac_taf_state_bytes(region, n, items_per_lane, history_size):
+    return int(lib().hpac_taf_state_bytes(int(region), int(n), int(items_per_lane), int(history_size)))
+
+
+def hpac_taf(inputs, outputs, history_size, prediction_size, rsd_threshold, level="wave", state=None, **kw):
+    """state: None (state within the launch) or a device buffer of
+    hpac_taf_state_bytes(...) bytes, zeroed before the first launch of a
+    sequence, carrying each lane's window and countdown across launches."""
     io = make_io(inputs, outputs, **kw)
-    _call("hpac_taf", lib().hpac_taf(ctypes.byref(io), history_size, prediction_size, rsd_threshold, _level(level)))
+    if state is not None:
+        need = hpac_taf_state_bytes(io.region, io.n, io.items_per_lane, history_size)
+        if need < 0:
+            raise ValueError("hpac_taf: no persistent state for these arguments")
+        _check_buf(state, need, "bytes", "state")
+    _call("hpac_taf", lib().hpac_taf(ctypes.byref(io), history_size, prediction_size, rsd_threshold, _level(level),
+                                     _addr(state)))
 
 
 def hpac_perfo(inputs, outputs, kind, param, offset=0, **kw):
@@ -320,7 +335,7 @@ def prepare(technique, inputs, outputs, **kw):
                   _level(kw.pop("level", "wave")))
     elif technique == "taf":
         params = (kw.pop("history_size"), kw.pop("prediction_size"), ctypes.c_float(kw.pop("rsd_threshold")),
-                  _level(kw.pop("level", "wave")))
+                  _level(kw.pop("level", "wave")), None)
     elif technique == "perfo":
         k = kw.pop("kind")
         params = (PERFO_KINDS[k] if isinstance(k, str) else int(k), kw.pop("param"), kw.pop("offset", 0))

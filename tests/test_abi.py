@@ -280,6 +280,22 @@ def test_grids_beyond_32_bit_lane_counts_are_rejected():
         assert "shift" in msg
 
 
+def test_persistent_taf_state_sizes_and_checks():
+    L = hpac.hpac_num_lanes(1000, 4)
+    assert hpac.hpac_taf_state_bytes(hpac.REGION_BS_PRICE, 1000, 4, 4) == L * (4 * 2 + 2) * 4
+    assert hpac.hpac_taf_state_bytes(hpac.REGION_BS_PRICE_GRAD, 1000, 4, 2) == L * (2 * 12 + 2) * 4
+    assert hpac.hpac_taf_state_bytes(hpac.REGION_BS_PRICE_REF, 1000, 4, 2) == -1
+    assert hpac.hpac_taf_state_bytes(hpac.REGION_BS_PRICE, 1000, 4, 9) == -1
+    assert hpac.hpac_taf_state_bytes(hpac.REGION_BS_PRICE, 1000, 0, 2) == -1
+    msg = expect(hpac.HPAC_EINVAL, hpac.hpac_taf, [FAKE] * 5, [FAKE] * 2, 4, 4, 0.01, n=1000, items_per_lane=4,
+                 stream=0, state=FAKE + 2)
+    assert "persistent_state" in msg
+    import torch
+    with pytest.raises(ValueError, match="state holds"):
+        hpac.hpac_taf([FAKE] * 5, [FAKE] * 2, 4, 4, 0.01, n=1000, items_per_lane=4, stream=0,
+                      state=torch.zeros(L * 10 * 4 - 1, dtype=torch.uint8))
+
+
 def test_short_or_mistyped_buffers_are_rejected_by_the_binding():
     """The binding checks every device buffer a kernel writes beyond the
     columns (trace, counters, the surrogate's queue, training partials):

@@ -18,7 +18,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import (SENTINEL, check_outputs, compare_decisions, mape_pair, run, say, to_dev, trace_dec)
+from gpu_util import (DEV, SENTINEL, check_outputs, compare_decisions, mape_pair, run, say, to_dev, trace_dec)
 from paper_2308_16877_amd import hpac, inputs
 
 pytestmark = pytest.mark.gpu
@@ -329,6 +329,58 @@ def replay_taf(name, y, tr, y_exact_gpu, sv, ipt, h, p, theta, level, block):
     L = oracle.num_lanes(n, ipt)
     mask = same_wave[(np.arange(n) % L) // 64]
     assert np.array_equal(y[:, mask], ora["out"][:, mask]), "replayed outputs differ on agreeing waves"
+
+
+@pytest.mark.parametrize("level,h,p,theta,block", [("wave", 4, 4, 0.01, 256), ("wave", 3, 2, 0.006, 192),
+                                                    ("thread", 3, 2, 0.006, 256), ("block", 3, 2, 0.006, 128)])
+def test_taf_persistent_state_continues_across_launches(level, h, p, theta, block):
+    """With a persistent state, launches of 6 and then 10 steps per lane over
+    consecutive parts of the inputs write exactly what one launch of 16
+    steps writes, and their traces are that launch's (windows, fills and
+    countdowns carried through the state, including approximate runs that
+    straddle the two launches); the two launches also match the oracle's
+    own two launches with a carried state, on the GPU exact kernel's values
+    (decision replay)."""
+    say("taf state %s h %d p %d" % (level, h, p))
+    x = inputs.periodic(65536, 8, jitter=1e-3)
+    n, a, b = x.shape[1], 6, 10
+    L = oracle.num_lanes(n, a + b)
+    n1 = a * L
+    assert oracle.num_lanes(n1, a) == L and oracle.num_lanes(n - n1, b) == L
+    kw = dict(block_size=block, history_size=h, prediction_size=p, rsd_threshold=theta, level=level)
+    need = hpac.hpac_taf_state_bytes(hpac.REGION_BS_PRICE, n1, a, h)
+    assert need == hpac.hpac_taf_state_bytes(hpac.REGION_BS_PRICE, n - n1, b, h) == L * (2 * h + 2) * 4
+    state = torch.zeros(need, dtype=torch.uint8, device=DEV)
+    xd = to_dev(x)
+    y1, t1, _ = run("taf", to_dev(x[:, :n1]), 2, a, state=state, **kw)
+    y2, t2, _ = run("taf", to_dev(x[:, n1:]), 2, b, state=state, **kw)
+    y, t, _ = run("taf", xd, 2, a + b, **kw)
+    assert np.array_equal(np.concatenate([y1, y2], axis=1), y)
+    assert np.array_equal(np.concatenate([t1.reshape(-1, a), t2.reshape(-1, b)], axis=1).ravel(), t)
+    gdec, _ = trace_dec(t)
+    assert (gdec == 1).any() and (gdec == 0).any()  # mixed decisions
+    # the oracle's two launches, state carried, on the GPU's exact values
+    ye = gpu_exact_values(xd)
+    _, sv = oracle.region_values_f32out(x)
+    st = oracle.taf_state(n1, a, h)
+    g = group_of(level, block)
+    o1 = oracle.taf(ye[:, :n1], sv[:, :n1], a, h, p, theta, band=GATE_BAND, group=g, state=st)
+    st["shape"] = (n - n1, b, h, 2)
+    o2 = oracle.taf(ye[:, n1:], sv[:, n1:], b, h, p, theta, band=GATE_BAND, group=g, state=st)
+    odec = np.concatenate([o1["dec"].reshape(-1, a), o2["dec"].reshape(-1, b)], axis=1).ravel()
+    ofrag = np.concatenate([o1["fragile"].reshape(-1, a), o2["fragile"].reshape(-1, b)], axis=1).ravel()
+    if level == "thread":
+        f = hpac.trace_fields(t)
+        gdec = np.where(f["active"], f["napprox"], -1)
+        odec = np.concatenate([o1["napprox"].reshape(-1, a), o2["napprox"].reshape(-1, b)], axis=1).ravel()
+        odec = np.where(np.concatenate([o1["dec"].reshape(-1, a), o2["dec"].reshape(-1, b)], axis=1).ravel() >= 0,
+                        odec, -1)
+    agree, compared, explained, _ = compare_decisions(gdec, odec, a + b, ofrag, lag=1)
+    assert agree >= 0.9999 * compared
+    oout = np.concatenate([o1["out"], o2["out"]], axis=1)
+    same = np.all(gdec.reshape(-1, a + b) == odec.reshape(-1, a + b), axis=1)[(np.arange(n) % L) // 64]
+    assert np.array_equal(y[:, same], oout[:, same])
+    say("  decisions agree %d/%d, explained %d" % (agree, compared, explained))
 
 
 # ------------------------------------------------------------- perforation

@@ -260,6 +260,53 @@ def test_taf_matches_brute_force(data):
         assert r["dec"][w * ipt + k] == d, (w, k)
 
 
+def _taf_two_launches(y, L, a, b, h, p, theta, group):
+    """Two launches with a carried state: the first a steps of every lane,
+    then the next b (launch shapes n = a L and b L keep the L lanes)."""
+    st = oracle.taf_state(a * L, a, h, y.shape[0])
+    r1 = oracle.taf(y[:, :a * L], None, a, h, p, theta, group=group, state=st)
+    st["shape"] = (b * L, b, h, y.shape[0])  # same lanes, the next steps
+    r2 = oracle.taf(y[:, a * L:], None, b, h, p, theta, group=group, state=st)
+    out = np.concatenate([r1["out"], r2["out"]], axis=1)
+    dec = np.concatenate([r1["dec"].reshape(-1, a), r2["dec"].reshape(-1, b)], axis=1).ravel()
+    return out, dec
+
+
+def test_taf_state_constant_outputs_closed_form_across_launches():
+    """C1 split over two launches (5 then 7 steps of one wave): the carried
+    window and countdown give the 7 of 12 approximate steps of one launch."""
+    y = np.full((2, 12 * W), 3.5)
+    out, dec = _taf_two_launches(y, W, 5, 7, 4, 4, 0.01, 64)
+    assert list(np.nonzero(dec == 1)[0]) == [4, 5, 6, 7, 9, 10, 11]
+    assert np.array_equal(out, y)
+
+
+@settings(max_examples=120, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(data=st.data())
+def test_taf_state_continues_across_launches(data):
+    """Two launches with a carried state equal one launch over both launches'
+    steps (outputs and per-(wave, step) decisions), and both equal the brute
+    force over the whole history of each lane."""
+    waves = data.draw(st.integers(1, 3))
+    L = waves * W
+    a, b = data.draw(st.integers(1, 7)), data.draw(st.integers(1, 7))
+    h = data.draw(st.integers(1, 4))
+    p = data.draw(st.integers(1, 5))
+    theta = data.draw(st.sampled_from([0.05, 0.3, 0.7]))
+    group = data.draw(st.sampled_from([1, 64, 128]))
+    n = (a + b) * L
+    vals = data.draw(st.lists(st.integers(1, 4), min_size=n, max_size=n))
+    y = np.stack([np.array(vals, np.float64), np.full(n, 2.0)])
+    out, dec = _taf_two_launches(y, L, a, b, h, p, theta, group)
+    one = oracle.taf(y, None, a + b, h, p, theta, group=group)
+    assert np.array_equal(out, one["out"])
+    assert np.array_equal(dec, one["dec"])
+    bout, bdec = brute.taf([tuple(y[:, i]) for i in range(n)], a + b, h, p, float(np.float32(theta)), group)
+    assert np.array_equal(out.T, np.array(bout))
+    for (w, k), d in bdec.items():
+        assert dec[w * (a + b) + k] == d, (w, k)
+
+
 # ---------------------------------------------------------------------- MAPE
 
 def test_mape_hand_example():
