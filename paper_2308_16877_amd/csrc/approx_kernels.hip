@@ -631,8 +631,10 @@ __global__ void __launch_bounds__(256) k_taf(KArgs a, int psize, float theta, fl
 // the vote fails, before the next step.  Only when the previous vote failed
 // is the next step's load issued speculatively before the region computes
 // (the vote is then likely to fail again); a pass wastes that load once.
-// Same decisions as k_taf at wave level.
-template <class R, int H>
+// Same decisions as k_taf at wave level.  kState: a launch with a
+// persistent state (compiled apart, so that the launch-scoped path carries
+// none of its code).
+template <class R, int H, bool kState>
 __global__ void __launch_bounds__(256) k_taf_wave(KArgs a, int psize, float theta, float *state) {
   __shared__ unsigned long long sums[4];
   const LaneGeom g;
@@ -653,7 +655,7 @@ __global__ void __launch_bounds__(256) k_taf_wave(KArgs a, int psize, float thet
   // previous launch's last passing vote (the same for every lane of a wave)
   const TafState<H, R::kOut> ts{state, a.L};
   int owed = 0;
-  if (state && g.l < a.L) ts.load(g.l, win, fill, owed);
+  if (kState && g.l < a.L) ts.load(g.l, win, fill, owed);
   owed = __builtin_amdgcn_readfirstlane(owed);
   int k = 0;
   for (; k < owed && k < a.ipt && g.wave_has(a, k); ++k) {
@@ -721,7 +723,7 @@ __global__ void __launch_bounds__(256) k_taf_wave(KArgs a, int psize, float thet
     prev_pass = pass;
     k = next;
   }
-  if (state && g.l < a.L) ts.store(g.l, win, fill, left);
+  if (kState && g.l < a.L) ts.store(g.l, win, fill, left);
   sink.end(st);
 }
 
@@ -919,8 +921,10 @@ hipError_t launch_iact(const LaunchCfg &c, const KArgs &a, int level, int table_
 
 template <class R, int LEVEL, int H>
 static void taf_go(const LaunchCfg &c, const KArgs &a, int p, float thr, float *st) {
-  if (LEVEL == kWaveLvl)
-    hipLaunchKernelGGL((k_taf_wave<R, H>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a, p, thr, st);
+  if (LEVEL == kWaveLvl && st)
+    hipLaunchKernelGGL((k_taf_wave<R, H, true>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a, p, thr, st);
+  else if (LEVEL == kWaveLvl)
+    hipLaunchKernelGGL((k_taf_wave<R, H, false>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a, p, thr, st);
   else
     hipLaunchKernelGGL((k_taf<R, LEVEL, H>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a, p, thr, st);
 }

@@ -16,7 +16,7 @@ def _write(path, rows):
 
 
 def test_kernel_match_by_name_and_template_prefix():
-    n = "void hpac::k_taf_wave<hpac::RegionBSPrice, 4>(hpac::KArgs, int, float)"
+    n = "void hpac::k_taf_wave<hpac::RegionBSPrice, 4, false>(hpac::KArgs, int, float, float*)"
     assert P._kernel_match(n, "k_taf_wave")
     assert not P._kernel_match(n, "k_taf")
     assert P._kernel_match("hpac::k_binomial<9, 1, true>(hpac::BoArgs)", "k_binomial<9, 1")
