@@ -512,6 +512,36 @@ def test_repeated_launches_are_bitwise_identical():
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
+@pytest.mark.parametrize("technique,level,tpw", [("iact", "wave", 1), ("iact", "block", 1), ("iact", "wave", 4),
+                                                  ("iact", "thread", 64), ("taf", "block", 1)])
+def test_stale_lds_of_a_previous_launch_is_never_read(technique, level, tpw):
+    """Tables and block tallies live in LDS, which a launch does not clear
+    for the next.  A first launch on one repeated option fills every wave's
+    tables with entries that would be hits for it (and leaves block tallies
+    at a passing majority); a second launch on the same option must still
+    start from empty tables and fresh windows: its first step computes
+    everywhere, and its decisions and outputs are the oracle's."""
+    x = inputs.constant(65536)
+    xd = to_dev(x)
+    kw = (dict(table_size=4, threshold=0.05, tables_per_wave=tpw, level=level) if technique == "iact"
+          else dict(history_size=2, prediction_size=2, rsd_threshold=0.01, level=level))
+    run(technique, xd, 2, 8, **kw)
+    y, t, cnt = run(technique, xd, 2, 8, **kw)
+    gdec, f = trace_dec(t)
+    assert np.all(gdec.reshape(-1, 8)[:, 0] == 0), "a first step approximated"
+    yv, sv = oracle.region_values_f32out(x)
+    if technique == "iact":
+        ora = oracle.iact(x, yv, sv, 8, 4, 0.05, tables_per_wave=tpw, group=group_of(level, 256))
+    else:
+        ora = oracle.taf(yv, sv, 8, 2, 2, 0.01, group=group_of(level, 256))
+    odec = ora["dec"]
+    if level == "thread":
+        gdec = np.where(f["active"], f["napprox"], -1)
+        odec = np.where(ora["dec"] >= 0, ora["napprox"], -1)
+    assert np.array_equal(gdec, odec)
+    check_outputs(y, ora["out"], ora["scale"], what="second launch")
+
+
 # --------------------------------------------------- full size (2^24 items)
 
 def test_full_size_config_against_oracle():
