@@ -377,7 +377,11 @@ __device__ __forceinline__ float dist2(const float (&x)[N], const float *e, int 
   return acc;
 }
 
-template <class R, int LEVEL, bool kInterleaved>
+// kOne: one table per wave (tpw == 1), compiled apart so that the
+// compiler sees the table count and insertion slot as wave-uniform values
+// (uniform search loop, no per-lane segment arithmetic) and the writer is
+// elected on integer keys by a folded DPP max.
+template <class R, int LEVEL, bool kInterleaved, bool kOne = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k_iact(KArgs a, int tsize, float theta,
                                                                                        int tpw) {
   extern __shared__ float lds[];
@@ -387,8 +391,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
   const LaneGeom g;
   const int lane = lane_id();
   const int wib = threadIdx.x >> 6;
+  if (kOne) tpw = 1;
   const int lpt = kWave / tpw;  // lanes per table
-  const int tab_in_wave = lane / lpt;
+  const int tab_in_wave = kOne ? 0 : lane / lpt;
   // word j of entry e of this lane's table: tab[(e * E + j) * ws]
   const int ws = kInterleaved ? tpw : 1;
   float *tab = kInterleaved ? lds + (size_t)wib * tpw * tsize * E + tab_in_wave
@@ -399,7 +404,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
   if (LEVEL == kBlock) tally.init();
   const float thr2 = theta * theta;
   const int seg0 = tab_in_wave * lpt;
-  const uint64_t segmask = lpt == kWave ? ~0ull : (((1ull << lpt) - 1) << seg0);
+  const uint64_t segmask = kOne || lpt == kWave ? ~0ull : (((1ull << lpt) - 1) << seg0);
   int cnt = 0, ins = 0;  // valid entries and insertions of this lane's table
   WaveStats st;
   float xa[R::kIn], xb[R::kIn];
@@ -440,9 +445,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
     const uint64_t cmask = ballot(computes);
     int writer0 = -1;
     if (cmask) {
-      const float key = computes ? md2 : -1.0f;
-      const float m = segment_max(key, lpt);
-      const uint64_t cand = ballot(computes && key == m);
+      uint64_t cand;
+      if (kOne) {
+        // keys: the distance's bits plus one (order-preserving for
+        // non-negative floats, +inf included), 0 for lanes that do not compute
+        // (the scan runs on every lane, outside the short-circuit below)
+        const uint32_t key = computes ? __float_as_uint(md2) + 1u : 0u;
+        const uint32_t m = wave_umax(key);
+        cand = ballot(computes && key == m);
+      } else {
+        const float key = computes ? md2 : -1.0f;
+        const float m = segment_max(key, lpt);
+        cand = ballot(computes && key == m);
+      }
       const uint64_t mine = cand & segmask;
       if (mine) {
         if (lane == lowest_lane(mine)) {
@@ -455,7 +470,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
         cnt = cnt < tsize ? cnt + 1 : tsize;
         ins += 1;
       }
-      const uint64_t cand0 = cand & (lpt == kWave ? ~0ull : ((1ull << lpt) - 1));
+      const uint64_t cand0 = cand & (kOne || lpt == kWave ? ~0ull : ((1ull << lpt) - 1));
       writer0 = cand0 ? lowest_lane(cand0) : -1;
       wave_lds_fence();
     }
@@ -899,16 +914,17 @@ struct IactL {
   template <class R>
   hipError_t go() const {
     const size_t lds = (size_t)iact_lds_bytes(c.region, c.block, t, tpw);
-    if (iact_interleaved(entry_floats<R>(), c.block, t, tpw)) return launch<R, true>(lds);
-    return launch<R, false>(lds);
+    if (tpw == 1) return launch<R, false, true>(lds);
+    if (iact_interleaved(entry_floats<R>(), c.block, t, tpw)) return launch<R, true, false>(lds);
+    return launch<R, false, false>(lds);
   }
-  template <class R, bool kIl>
+  template <class R, bool kIl, bool kOne>
   hipError_t launch(size_t lds) const {
     const dim3 g = grid_for(a, c.block), b(c.block);
     switch (level) {
-      case kThread: hipLaunchKernelGGL((k_iact<R, kThread, kIl>), g, b, lds, c.stream, a, t, thr, tpw); break;
-      case kWaveLvl: hipLaunchKernelGGL((k_iact<R, kWaveLvl, kIl>), g, b, lds, c.stream, a, t, thr, tpw); break;
-      default: hipLaunchKernelGGL((k_iact<R, kBlock, kIl>), g, b, lds, c.stream, a, t, thr, tpw); break;
+      case kThread: hipLaunchKernelGGL((k_iact<R, kThread, kIl, kOne>), g, b, lds, c.stream, a, t, thr, tpw); break;
+      case kWaveLvl: hipLaunchKernelGGL((k_iact<R, kWaveLvl, kIl, kOne>), g, b, lds, c.stream, a, t, thr, tpw); break;
+      default: hipLaunchKernelGGL((k_iact<R, kBlock, kIl, kOne>), g, b, lds, c.stream, a, t, thr, tpw); break;
     }
     return hipGetLastError();
   }

@@ -43,6 +43,27 @@ __device__ __forceinline__ float wave_max(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// One DPP step of an unsigned max-scan, v = max(v, v of the lane CTRL
+// selects); lanes with no source, and rows ROW_MASK leaves out, see 0, the
+// scan's identity.  The compiler folds the DPP move into the max.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_umax(uint32_t v) {
+  const uint32_t s = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xf, true);
+  return v > s ? v : s;
+}
+
+// Maximum of an unsigned key over the wave, returned to every lane (the
+// same scan as wave_max, one instruction per step).
+__device__ __forceinline__ uint32_t wave_umax(uint32_t v) {
+  v = dpp_umax<0x111, 0xf>(v);  // row_shr:1
+  v = dpp_umax<0x112, 0xf>(v);  // row_shr:2
+  v = dpp_umax<0x114, 0xf>(v);  // row_shr:4
+  v = dpp_umax<0x118, 0xf>(v);  // row_shr:8
+  v = dpp_umax<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_umax<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 // Maximum of v over aligned segments of `seg` lanes (seg a power of two up to
 // 64), returned to every lane of the segment.
 __device__ __forceinline__ float segment_max(float v, int seg) {
