@@ -82,7 +82,7 @@ __device__ __forceinline__ void queue_flush(const MlpArgs &a, const int32_t *sta
 // gather is paid once per wave rather than once per 64 items.
 __global__ void __launch_bounds__(256) k_mlp_infer(MlpArgs a) {
   __shared__ float4 xs[4][64][2];  // per wave: normalised inputs of its 64 items, zero-padded to 8
-  __shared__ float ys[4][64][2];  // per wave: outputs
+  __shared__ float ys[4][64][2];  // per wave: the network's normalised outputs
   __shared__ int32_t qstage[4][kQueueStage];
   const int lane = lane_id();
   const int w = threadIdx.x >> 6;
@@ -188,14 +188,15 @@ __global__ void __launch_bounds__(256) k_mlp_infer(MlpArgs a) {
       D3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W3[1], h2[1], D3, 0, 0, 0);
       // rows 0 and 1 (the two outputs) live in lanes 0..15, slots 0 and 1
       if (g == 0) {
-        ys[w][16 * tn + r][0] = out_map(a, 0, D3[0]);
-        ys[w][16 * tn + r][1] = out_map(a, 1, D3[1]);
+        ys[w][16 * tn + r][0] = D3[0];
+        ys[w][16 * tn + r][1] = D3[1];
       }
     }
     wave_lds_fence();
     if (active && inside) {
-      a.out[0][i] = ys[w][lane][0];
-      a.out[1][i] = ys[w][lane][1];
+      // the output map once per item, each lane on its own item
+      a.out[0][i] = out_map(a, 0, ys[w][lane][0]);
+      a.out[1][i] = out_map(a, 1, ys[w][lane][1]);
     }
   }
   if (staged > 0) {
