@@ -826,6 +826,11 @@ struct ExactL {
   const KArgs &a;
   template <class R>
   hipError_t go() const {
+    if (a.ipt > 1) return run<Streamed<R>>();
+    return run<R>();
+  }
+  template <class R>
+  hipError_t run() const {
     if (a.trace || a.counters)
       hipLaunchKernelGGL((k_exact<R, true>), counted_grid(a, c.block), dim3(c.block), 0, c.stream, a);
     else if constexpr (IsPaired<R>::value) {
@@ -911,8 +916,9 @@ struct IactL {
   int level, t;
   float thr;
   int tpw;
-  template <class R>
+  template <class R0>
   hipError_t go() const {
+    using R = Streamed<R0>;
     const size_t lds = (size_t)iact_lds_bytes(c.region, c.block, t, tpw);
     if (tpw == 1) return launch<R, false, true>(lds);
     if (iact_interleaved(entry_floats<R>(), c.block, t, tpw)) return launch<R, true, false>(lds);
@@ -965,8 +971,9 @@ struct TafL {
   int level, h, p;
   float thr;
   float *st;
-  template <class R>
+  template <class R0>
   hipError_t go() const {
+    using R = Streamed<R0>;
     switch (level) {
       case kThread: taf_h<R, kThread>(c, a, h, p, thr, st); break;
       case kWaveLvl: taf_h<R, kWaveLvl>(c, a, h, p, thr, st); break;

@@ -39,4 +39,28 @@ struct WithIo : Base {
   using io = Io;
 };
 
+// The same columns read and written with nontemporal (streaming) accesses.
+// A grid-stride loop over several items per lane keeps many widely spaced
+// streams in flight (each lane's consecutive items lie L apart), and there
+// streaming accesses measured faster; a launch of one item per lane, one
+// contiguous sweep, measured slower with them, so it keeps ordinary ones.
+template <class Io>
+struct StreamIo {
+  using elem = typename Io::elem;
+  __device__ __forceinline__ static float load(const void *p, int64_t i) {
+    const elem e = __builtin_nontemporal_load(&((const elem *)p)[i]);
+    return Io::load(&e, 0);
+  }
+  __device__ __forceinline__ static void store(void *p, int64_t i, float v) {
+    elem e;
+    Io::store(&e, 0, v);
+    __builtin_nontemporal_store(e, &((elem *)p)[i]);
+  }
+};
+
+template <class Base>
+struct Streamed : Base {
+  using io = StreamIo<typename Base::io>;
+};
+
 }  // namespace hpac

@@ -69,8 +69,8 @@ def short_name(name):
 BS_KERNELS = ("k_exact", "k_iact", "k_taf", "k_taf_wave", "k_perfo", "k_perfo_dense")
 # the kernel each technique of the benchmark step launches (trace names)
 STEP_KERNELS = {"exact": "hpac::k_exact<hpac::RegionBSPrice, false>",
-                "iact": "hpac::k_iact<hpac::RegionBSPrice, 1, false, true>",
-                "taf": "hpac::k_taf_wave<hpac::RegionBSPrice, 4, false>",
+                "iact": "hpac::k_iact<hpac::Streamed<hpac::RegionBSPrice>, 1, false, true>",
+                "taf": "hpac::k_taf_wave<hpac::Streamed<hpac::RegionBSPrice>, 4, false>",
                 "perfo": "hpac::k_perfo_dense<hpac::RegionBSPrice>"}
 
 
