@@ -43,6 +43,8 @@ TECHS = {
     "perfo": ("perfo", 20, dict(kind="small", param=10, offset=0)),
 }
 KERNEL_NAMES = {"exact": "k_exact", "iact": "k_iact", "taf": "k_taf_wave", "perfo": "k_perfo_dense"}
+# the timed region records each launch's events on one step in EVENT_EVERY
+EVENT_EVERY = 4
 # VALU issue peak: 256 CUs x 4 SIMDs x 32 FP32 lanes per clock x 2.4 GHz = 78.6
 # tera lane-instructions per second (157.3 TFLOP/s in FMAs).  A wave64 FP32
 # instruction whose operands are all vector registers or constants issues in
@@ -206,23 +208,29 @@ def run_workload(torch, hpac, x_copies, n, steps, warmup, with_stats=True, min_w
         if w >= warmup:
             torch.cuda.synchronize()  # host time then follows the GPU's
     torch.cuda.synchronize()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)] for _ in range(steps)]
+    # per-kernel events on every EVENT_EVERY-th step of the timed region only:
+    # an event between two launches costs the step a few microseconds
+    timed = [s for s in range(steps) if s % EVENT_EVERY == 0]
+    ev = {s: [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)] for s in timed}
     t0 = time.perf_counter()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     start.record(stream)
     for s in range(steps):
         c = s % len(x_copies)
-        ev[s][0].record(stream)
+        e = ev.get(s)
+        if e:
+            e[0].record(stream)
         for j, t in enumerate(names):
             prep[t][c]()
-            ev[s][j + 1].record(stream)
+            if e:
+                e[j + 1].record(stream)
     stop.record(stream)
     host_s = time.perf_counter() - t0
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     total_ms = start.elapsed_time(stop)
-    per = {t: [ev[s][j].elapsed_time(ev[s][j + 1]) for s in range(steps)] for j, t in enumerate(names)}
+    per = {t: [ev[s][j].elapsed_time(ev[s][j + 1]) for s in timed] for j, t in enumerate(names)}
     res = {"total_ms": total_ms, "wall_s": wall, "host_enqueue_s": host_s, "warmup_steps_run": w,
            "per_kernel_ms": {t: sum(v) / len(v) for t, v in per.items()},
            "per_kernel_median_ms": {t: sorted(v)[len(v) // 2] for t, v in per.items()},
