@@ -81,7 +81,9 @@ __device__ __forceinline__ void queue_flush(const MlpArgs &a, const int32_t *sta
 // 64-item chunks (chunk = wave id + k * waves in the grid), so the weight
 // gather is paid once per wave rather than once per 64 items.
 __global__ void __launch_bounds__(256) k_mlp_infer(MlpArgs a) {
-  __shared__ float4 xs[4][64][2];  // per wave: normalised inputs of its 64 items, zero-padded to 8
+  // per wave: the BF16 normalised inputs of its 64 items in the B-operand
+  // layout of layer 1 (slots 5..7 zero), and a zero row 64 for lane groups 1..3
+  __shared__ bf16x8 xs[4][65];
   __shared__ float ys[4][64][2];  // per wave: the network's normalised outputs
   __shared__ int32_t qstage[4][kQueueStage];
   const int lane = lane_id();
@@ -120,20 +122,38 @@ __global__ void __launch_bounds__(256) k_mlp_infer(MlpArgs a) {
 #pragma unroll
   for (int j = 0; j < 4; ++j) B3[j] = (4 * g + j < 2) ? a.params[kOffB3 + 4 * g + j] : 0.0f;
 
+  if (lane == 0) {
+    bf16x8 z;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) z[j] = (__bf16)0.0f;
+    xs[w][64] = z;
+  }
   const int64_t chunks = (a.n + 63) >> 6;
   const int64_t waves = (int64_t)gridDim.x * 4;
   int staged = 0;  // wave-uniform
+  // inputs of the wave's next chunk, loaded one chunk ahead
+  float xn[5];
+  {
+    const int64_t i0 = ((int64_t)blockIdx.x * 4 + w) * 64 + lane;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) xn[j] = i0 < a.n ? a.in[j][i0] : 0.0f;
+  }
 #pragma unroll 1
   for (int64_t ch = (int64_t)blockIdx.x * 4 + w; ch < chunks; ch += waves) {
     const int64_t i = ch * 64 + lane;
     const bool active = i < a.n;
-    // load, box test, queue the items outside the box
+    // box test, then the loads of the next chunk go out while this one computes
     float x[5];
     bool inside = active;
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
-      x[j] = active ? a.in[j][i] : 0.0f;
+      x[j] = xn[j];
       inside = inside && x[j] >= a.box_lo[j] && x[j] <= a.box_hi[j];
+    }
+    if (ch + waves < chunks) {  // wave-uniform
+      const int64_t inx = i + waves * 64;
+#pragma unroll
+      for (int j = 0; j < 5; ++j) xn[j] = inx < a.n ? a.in[j][inx] : 0.0f;
     }
     const uint64_t out_mask = ballot(active && !inside);
     // the previous chunk's LDS reads are done before anything is rewritten
@@ -151,19 +171,19 @@ __global__ void __launch_bounds__(256) k_mlp_infer(MlpArgs a) {
     float xh[5];
 #pragma unroll
     for (int j = 0; j < 5; ++j) xh[j] = (x[j] - a.in_center[j]) * a.in_scale[j];
-    xs[w][lane][0] = make_float4(xh[0], xh[1], xh[2], xh[3]);
-    xs[w][lane][1] = make_float4(xh[4], 0.0f, 0.0f, 0.0f);
+    {
+      bf16x8 v;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = (__bf16)(j < 5 ? xh[j < 5 ? j : 0] : 0.0f);
+      xs[w][lane] = v;
+    }
     wave_lds_fence();
 
 #pragma unroll 2
     for (int tn = 0; tn < 4; ++tn) {
       // B operand of layer 1: inputs of item 16 tn + r in slots 0..7 of lane
       // group 0, zeros elsewhere
-      const float4 lo = xs[w][16 * tn + r][0], hi = xs[w][16 * tn + r][1];
-      const float xv[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-      bf16x8 xb;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) xb[j] = (__bf16)(g == 0 ? xv[j] : 0.0f);
+      const bf16x8 xb = xs[w][g == 0 ? 16 * tn + r : 64];
       floatx4 D1[4];
 #pragma unroll
       for (int tm = 0; tm < 4; ++tm) D1[tm] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W1[tm], xb, B1[tm], 0, 0, 0);
