@@ -321,18 +321,18 @@ __global__ void __launch_bounds__(256) k_perfo(KArgs a, int kind, int param, int
 // ranges [kL, (k+1)L) of the kept steps k -- can be evaluated by any lanes:
 // one item per lane, workgroups mapped onto the kept ranges, dropped ranges
 // never launched.  The outputs are those of k_perfo bit for bit.
+// Kept steps repeat with period M: SMALL keeps every position of a period
+// but `special`, LARGE keeps only `special`.  The grid is (workgroups per
+// step, kept positions per period, periods), so a workgroup finds its step
+// without an integer division (one on each wave's path to its first load
+// cost the launch 8%).
 template <class R>
-__global__ void __launch_bounds__(256) k_perfo_dense(KArgs a, int blocks_per_step, int M, int kept_per_period,
-                                                     int special, int large) {
-  // block -> j-th kept step.  Kept steps repeat with period M: SMALL keeps
-  // every position of a period but `special`, LARGE keeps only `special`.
-  const int b = blockIdx.x;
-  const int j = b / blocks_per_step;
-  const int P = j / kept_per_period;
-  const int r = j - P * kept_per_period;
+__global__ void __launch_bounds__(256) k_perfo_dense(KArgs a, int64_t steps, int M, int special, int large) {
+  const int r = blockIdx.y;
   const int s = large ? special : (r < special ? r : r + 1);
-  const int64_t k = (int64_t)P * M + s;
-  const int64_t i = k * a.L + (int64_t)(b - j * blocks_per_step) * blockDim.x + threadIdx.x;
+  const int64_t k = (int64_t)blockIdx.z * M + s;
+  if (k >= steps) return;  // past the last step of a partial period
+  const int64_t i = k * a.L + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t end = (k + 1) * a.L < a.n ? (k + 1) * a.L : a.n;
   if (i < end) {
     float x[R::kIn], y[R::kOut];
@@ -849,8 +849,10 @@ hipError_t launch_exact(const LaunchCfg &c, const KArgs &a) {
   return with_region<true>(c.region, c.dtype, ExactL{c, a});
 }
 
-// A dispatch's grid size is a 32-bit count of lanes.
+// A dispatch's grid size is a 32-bit count of lanes per dimension; the
+// second and third dimensions are kept within 65535 workgroups.
 constexpr int64_t kMaxGridLanes = 0xFFFFFFFFll;
+constexpr int64_t kMaxGridYZ = 65535;
 
 struct PerfoL {
   const LaunchCfg &c;
@@ -899,9 +901,10 @@ struct PerfoL {
     }
     if (kept == 0) return hipSuccess;
     const int64_t bps = (a.L + c.block - 1) / c.block;
-    if (kept * bps * c.block > kMaxGridLanes) return counted();
-    hipLaunchKernelGGL((k_perfo_dense<R>), dim3((unsigned)(kept * bps)), dim3(c.block), 0, c.stream, a, (int)bps,
-                       M, kept_per_period, special, kind == kLarge ? 1 : 0);
+    const int64_t periods = (steps + M - 1) / M;
+    if (bps * c.block > kMaxGridLanes || periods > kMaxGridYZ || kept_per_period > kMaxGridYZ) return counted();
+    hipLaunchKernelGGL((k_perfo_dense<R>), dim3((unsigned)bps, (unsigned)kept_per_period, (unsigned)periods),
+                       dim3(c.block), 0, c.stream, a, steps, M, special, kind == kLarge ? 1 : 0);
     return hipGetLastError();
   }
 };

@@ -444,6 +444,10 @@ DENSE_CASES = [
     ("ini30", "ini", 30, 0, 4, 10007),
     ("fini25", "fini", 25, 0, 4, 10007),
     ("fini100", "fini", 100, 0, 4, 999),
+    # a period longer than the launch: most of the grid's positions fall past the last step
+    ("small50_off7", "small", 50, 7, 20, 65536),
+    # more periods than a grid dimension holds: the per-unit kernel runs instead
+    ("large1_65536_steps", "large", 1, 0, 65536, 65536 * 64),
 ]
 
 
