@@ -510,6 +510,8 @@ static hpac_status check_hydro_state(const char *fn, const hpac_hydro_state *S, 
 static hpac::HydroArgs hydro_args(const hpac_hydro_params *P, const hpac_hydro_state *S) {
   hpac::HydroArgs a = {};
   a.n = P->n;
+  a.dn = hpac::DivBy::of(P->n);
+  a.dm = hpac::DivBy::of(P->n + 1);
   a.E = (int64_t)P->n * P->n * P->n;
   a.Nn = (int64_t)(P->n + 1) * (P->n + 1) * (P->n + 1);
   a.W = hpac::hydro_lanes(a.E, 1) / 64;

@@ -189,9 +189,10 @@ __device__ __forceinline__ void hourglass(const float (&x)[8][3], const float (&
 struct ElemIdx {
   int64_t z;
   int64_t node0;  // node of corner 0
-  __device__ ElemIdx(int64_t z_, int n) : z(z_) {
-    const int64_t m = n + 1;
-    const int64_t i = z % n, j = (z / n) % n, k = z / ((int64_t)n * n);
+  __device__ ElemIdx(int64_t z_, const DivBy &dn) : z(z_) {
+    const int64_t n = dn.d, m = n + 1;
+    const uint32_t t = dn.quo((uint32_t)z_), k = dn.quo(t);
+    const int64_t i = z_ - (int64_t)t * n, j = (int64_t)t - (int64_t)k * n;
     node0 = i + m * (j + m * k);
   }
   __device__ int64_t node(int c, int n) const {
@@ -282,8 +283,9 @@ __device__ __forceinline__ double block_min(double v, double *red) {
 __global__ void __launch_bounds__(256) k_hydro_init_elem(HydroArgs a, double e_origin) {
   const int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (z >= a.E) return;
-  const int n = a.n;
-  const int64_t i = z % n, j = (z / n) % n, k = z / ((int64_t)n * n);
+  const int64_t n = a.n;
+  const uint32_t t = a.dn.quo((uint32_t)z), kk = a.dn.quo(t);
+  const int64_t i = z - (int64_t)t * n, j = (int64_t)t - (int64_t)kk * n, k = kk;
   float x[8][3], B[8][3];
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
@@ -308,7 +310,8 @@ __global__ void __launch_bounds__(256) k_hydro_init_node(HydroArgs a) {
   if (v >= a.Nn) return;
   const int n = a.n;
   const int64_t m = n + 1;
-  const int64_t i = v % m, j = (v / m) % m, k = v / (m * m);
+  const uint32_t t = a.dm.quo((uint32_t)v), kk = a.dm.quo(t);
+  const int64_t i = v - (int64_t)t * m, j = (int64_t)t - (int64_t)kk * m, k = kk;
   a.x[0][v] = a.h * (float)i;
   a.x[1][v] = a.h * (float)j;
   a.x[2][v] = a.h * (float)k;
@@ -398,7 +401,7 @@ __global__ void __launch_bounds__(256) k_hydro_force(HydroArgs a) {
     }
     bool crit = false, voted = false;
     if (active) {
-      const ElemIdx ei(z, n);
+      const ElemIdx ei(z, a.dn);
       float x[8][3], u[8][3], B[8][3];
       gather3(a.x, ei, n, x);
       gather3(a.u, ei, n, u);
@@ -514,7 +517,8 @@ __global__ void __launch_bounds__(256) k_hydro_node(HydroArgs a) {
   if (v >= a.Nn) return;
   const int n = a.n;
   const int64_t m = n + 1, E = a.E;
-  const int64_t i = v % m, j = (v / m) % m, k = v / (m * m);
+  const uint32_t t = a.dm.quo((uint32_t)v), kk = a.dm.quo(t);
+  const int64_t i = v - (int64_t)t * m, j = (int64_t)t - (int64_t)kk * m, k = kk;
   float F[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
@@ -590,7 +594,7 @@ __global__ void __launch_bounds__(256) k_hydro_eos(HydroArgs a) {
   }
   bool crit = false, voted = false;
   if (active) {
-    const ElemIdx ei(z, n);
+    const ElemIdx ei(z, a.dn);
     float x[8][3], u0[8][3], u1[8][3], B[8][3];
     gather3(a.x, ei, n, x);
     gather3(a.u, ei, n, u0);

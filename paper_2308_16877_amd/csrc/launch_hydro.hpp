@@ -11,8 +11,32 @@ constexpr int kHgExact = 0, kHgTafWave = 1, kHgTafThread = 2, kHgPerfo = 3, kHgN
 constexpr int kEosExact = 0, kEosTafWave = 1, kEosTafThread = 2, kEosTafBlock = 3;
 constexpr int kHydroBlock = 256;  // elements of a workgroup, the block-level decision group
 
+// Division by a fixed divisor d >= 1 of dividends below 2^31 as one 64-bit
+// multiply and a shift (Granlund and Montgomery's round-up method): with
+// l = ceil(log2 d) and M = ceil(2^(31+l) / d), M d = 2^(31+l) + e with
+// 0 <= e < d <= 2^l, so x M / 2^(31+l) exceeds x / d by less than 1/d and
+// floors to the same integer.  Element and node indices of a mesh of up to
+// 1000 elements per side are below 2^31.
+struct DivBy {
+  uint64_t M;
+  int s;
+  int32_t d;
+  static constexpr DivBy of(int32_t d) {
+    int l = 0;
+    while ((int64_t(1) << l) < d) ++l;
+    return DivBy{((uint64_t(1) << (31 + l)) + (uint64_t)d - 1) / (uint64_t)d, 31 + l, d};
+  }
+  __host__ __device__ constexpr uint32_t quo(uint32_t x) const { return (uint32_t)(((uint64_t)x * M) >> s); }
+};
+static_assert(DivBy::of(1).quo(0x7fffffffu) == 0x7fffffffu && DivBy::of(2).quo(0x7fffffffu) == 0x3fffffffu);
+static_assert(DivBy::of(3).quo(0x7fffffffu) == 0x7fffffffu / 3 && DivBy::of(3).quo(5) == 1 && DivBy::of(3).quo(6) == 2);
+static_assert(DivBy::of(90).quo(728999) == 8099 && DivBy::of(90).quo(8099) == 89 && DivBy::of(91).quo(753571) == 8281 && DivBy::of(91).quo(753570) == 8280);
+static_assert(DivBy::of(1000).quo(999999999) == 999999 && DivBy::of(1001).quo(1003003000) == 1002000);
+static_assert(DivBy::of(0x7fffffff).quo(0x7ffffffeu) == 0 && DivBy::of(0x7fffffff).quo(0x7fffffffu) == 1);
+
 struct HydroArgs {
   int n;                  // elements per side
+  DivBy dn, dm;           // division by n and by n + 1 (nodes per side)
   int64_t E, Nn, W;       // elements, nodes, waves of the element loop (one element per lane)
   float h;                // initial edge of an element
   float gamma, cq, cl, khg;
