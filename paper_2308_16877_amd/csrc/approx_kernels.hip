@@ -405,7 +405,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
   const float thr2 = theta * theta;
   const int seg0 = tab_in_wave * lpt;
   const uint64_t segmask = kOne || lpt == kWave ? ~0ull : (((1ull << lpt) - 1) << seg0);
-  int cnt = 0, ins = 0;  // valid entries and insertions of this lane's table
+  int cnt = 0, ins = 0;  // valid entries of this lane's table, and its next slot (insertions mod size)
   WaveStats st;
   float xa[R::kIn], xb[R::kIn];
   load_first<R>(a, g, true, xa);
@@ -461,14 +461,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
       const uint64_t mine = cand & segmask;
       if (mine) {
         if (lane == lowest_lane(mine)) {
-          float *slot = tab + (ins % tsize) * E * ws;
+          float *slot = tab + ins * E * ws;
 #pragma unroll
           for (int j = 0; j < R::kIn; ++j) slot[j * ws] = x[j];
 #pragma unroll
           for (int o = 0; o < R::kOut; ++o) slot[(R::kIn + o) * ws] = y[o];
         }
         cnt = cnt < tsize ? cnt + 1 : tsize;
-        ins += 1;
+        ins = ins + 1 == tsize ? 0 : ins + 1;
       }
       const uint64_t cand0 = cand & (kOne || lpt == kWave ? ~0ull : ((1ull << lpt) - 1));
       writer0 = cand0 ? lowest_lane(cand0) : -1;
