@@ -223,6 +223,15 @@ __global__ void __launch_bounds__(256) k_exact(KArgs a) {
   if (kStats) {
     const int64_t blocks = (a.L + blockDim.x - 1) / blockDim.x;
     for (int64_t b = blockIdx.x; b < blocks; b += gridDim.x) run_block(b);
+  } else if (a.ipt == 1) {
+    // one item per lane: no next step to prefetch
+    const LaneGeom g;
+    if (g.active(a, 0)) {
+      float x[R::kIn], y[R::kOut];
+      load_inputs<R>(a, g.item(a, 0), x);
+      eval_at<R>(x, g.item(a, 0), y);
+      store_outputs<R>(a, g.item(a, 0), y);
+    }
   } else {
     run_block(blockIdx.x);  // the uncounted grid is the full grid
   }
