@@ -200,10 +200,13 @@ def run_workload(torch, hpac, x_copies, n, steps, warmup, with_stats=True, min_w
     # argument marshalling done once per (technique, input copy)
     prep = {t: [hpac.prepare(TECHS[t][0], xs, outs[t], items_per_lane=TECHS[t][1], block_size=256,
                              stream=stream, **TECHS[t][2]) for xs in x_copies] for t in names}
+    # launch j of step s reads copy (s + j) mod 3: consecutive launches never
+    # read the same copy, and a copy was last read three launches earlier
+    nc = len(x_copies)
     w, tw = 0, time.perf_counter()
     while w < warmup or time.perf_counter() - tw < min_warm_s:
-        for t in names:
-            prep[t][w % len(x_copies)]()
+        for j, t in enumerate(names):
+            prep[t][(w + j) % nc]()
         w += 1
         if w >= warmup:
             torch.cuda.synchronize()  # host time then follows the GPU's
@@ -217,12 +220,11 @@ def run_workload(torch, hpac, x_copies, n, steps, warmup, with_stats=True, min_w
     stop = torch.cuda.Event(enable_timing=True)
     start.record(stream)
     for s in range(steps):
-        c = s % len(x_copies)
         e = ev.get(s)
         if e:
             e[0].record(stream)
         for j, t in enumerate(names):
-            prep[t][c]()
+            prep[t][(s + j) % nc]()
             if e:
                 e[j + 1].record(stream)
     stop.record(stream)
