@@ -955,12 +955,14 @@ hipError_t launch_iact(const LaunchCfg &c, const KArgs &a, int level, int table_
 
 template <class R, int LEVEL, int H>
 static void taf_go(const LaunchCfg &c, const KArgs &a, int p, float thr, float *st) {
-  if (LEVEL == kWaveLvl && st)
-    hipLaunchKernelGGL((k_taf_wave<R, H, true>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a, p, thr, st);
-  else if (LEVEL == kWaveLvl)
-    hipLaunchKernelGGL((k_taf_wave<R, H, false>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a, p, thr, st);
-  else
+  if constexpr (LEVEL == kWaveLvl) {
+    if (st)
+      hipLaunchKernelGGL((k_taf_wave<R, H, true>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a, p, thr, st);
+    else
+      hipLaunchKernelGGL((k_taf_wave<R, H, false>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a, p, thr, st);
+  } else {
     hipLaunchKernelGGL((k_taf<R, LEVEL, H>), grid_for(a, c.block), dim3(c.block), 0, c.stream, a, p, thr, st);
+  }
 }
 
 template <class R, int LEVEL>

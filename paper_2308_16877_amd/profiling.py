@@ -23,6 +23,7 @@ import csv
 import hashlib
 import json
 import os
+import re
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -62,8 +63,10 @@ def kernel_source_sha(kernel="k_exact"):
 
 
 def short_name(name):
+    """The kernel's name without its parameter list, nested template
+    closers written ">>" whichever demangler printed the name."""
     base = name.split("(")[0].replace("void ", "")
-    return base
+    return re.sub(r">\s+(?=>)", ">", base)
 
 
 BS_KERNELS = ("k_exact", "k_iact", "k_taf", "k_taf_wave", "k_perfo", "k_perfo_dense")

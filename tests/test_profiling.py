@@ -63,3 +63,11 @@ def test_trace_summary_averages_the_timed_dispatches(tmp_path):
     text = (tmp_path / "o.txt").read_text()
     assert "dispatches 2..4" in text
     assert "iact (%s): 20.0 (HIP events 25.0)" % name in text
+
+
+def test_trace_names_with_spaced_template_closers_match():
+    """A demangler that writes nested closers as "> >" names the same kernel."""
+    name = "hpac::k_taf_wave<hpac::WithIo<hpac::Streamed<hpac::RegionBSPrice>>, 4, false>"
+    spaced = name.replace(">>", "> >") + "(hpac::KArgs, int, float, float*)"
+    assert P.short_name(spaced) == name
+    assert P._kernel_match(spaced, "k_taf_wave")
