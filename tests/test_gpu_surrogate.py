@@ -104,11 +104,14 @@ def inference_bound(x, w, nm):
     return b * nm["out_scale"][:, None]
 
 
+@pytest.mark.parametrize("n", [1 << 16, (1 << 20) + 37])
 @pytest.mark.parametrize("shift", [0.0, surrogate.PRICE_SHIFT])
-def test_mfma_inference_matches_oracle_forward(shift):
+def test_mfma_inference_matches_oracle_forward(shift, n):
     """With log outputs (shift > 0) the bound on v = yh * scale + mean maps
-    through exp: |dy| <= (y + shift) (exp(b) - 1) plus FP32 expf rounding."""
-    n = 1 << 16
+    through exp: |dy| <= (y + shift) (exp(b) - 1) plus FP32 expf rounding.
+    n = 2^20 + 37 ends in a 37-item chunk and gives every wave of the
+    persistent grid five or six chunks, each loaded while the previous one
+    computes."""
     x = inputs.uniform_box(n, seed=53).astype(np.float32)
     w = f32(surrogate.init_params(4))
     labels = np.stack(oracle.bs_price(*x)[:2])
