@@ -64,7 +64,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-structured", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=1 << 24)
-    p.add_argument("--legs-out", default=os.path.join("gpurun_out", "bench_legs.json"),
+    p.add_argument("--legs-out", default=os.path.join("results", "bench_legs.json"),
                    help="file for the full results of every leg (the printed line summarises them)")
     p.add_argument("--pmc-probe", action="store_true",
                    help="only launch each kernel of the step three times plus a 256 MiB copy probe, untimed, "

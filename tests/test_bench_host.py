@@ -85,7 +85,7 @@ def test_headline_line_is_short_and_complete():
            "sample": "first 16777216 of the 16777216 items, all four legs of one step (exact, iACT, TAF, "
                      "perforation), 0.8 s wall"}
     summary = bench.leg_summary(_fake_legs())
-    line = bench.headline(args, res, tech, 1.3e11, 0.36, "iact", roofline, cpu, summary, "gpurun_out/bench_legs.json")
+    line = bench.headline(args, res, tech, 1.3e11, 0.36, "iact", roofline, cpu, summary, "results/bench_legs.json")
     text = json.dumps(line)
     assert len(text.encode()) < 4096, len(text)
     back = json.loads(text)
