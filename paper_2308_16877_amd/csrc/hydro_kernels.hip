@@ -499,8 +499,20 @@ __global__ void __launch_bounds__(256) k_hydro_force(HydroArgs a) {
 
 __global__ void __launch_bounds__(256) k_hydro_dt(HydroArgs a, int64_t parts) {
   __shared__ double red[256];
+  // sixteen independent loads per thread in flight at once: the partials
+  // were just written by every XCD, so each round trip is a memory latency
+  constexpr int kU = 16;
   double m = INFINITY;
-  for (int64_t b = threadIdx.x; b < parts; b += blockDim.x) m = fmin(m, a.dt_partials[b]);
+  for (int64_t b0 = threadIdx.x; b0 < parts; b0 += (int64_t)blockDim.x * kU) {
+    double v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t b = b0 + (int64_t)u * blockDim.x;
+      v[u] = b < parts ? a.dt_partials[b] : INFINITY;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) m = fmin(m, v[u]);
+  }
   m = block_min(m, red);
   if (threadIdx.x == 0) {
     const double dt = fmin(m, a.growth * a.clock[1]);
