@@ -366,8 +366,18 @@ __global__ void __launch_bounds__(64) k_mlp_grad(MlpGradArgs a) {
 __global__ void __launch_bounds__(256) k_mlp_adam(AdamArgs a) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= kNumParams) return;
+  // the partials summed in workgroup order; sixteen loads in flight at a
+  // time instead of one memory latency per partial
+  constexpr int kU = 16;
   float g = 0.0f;
-  for (int64_t b = 0; b < a.blocks; ++b) g += a.grad_partials[b * kNumParams + p];
+  for (int64_t b0 = 0; b0 < a.blocks; b0 += kU) {
+    float v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) v[u] = b0 + u < a.blocks ? a.grad_partials[(b0 + u) * kNumParams + p] : 0.0f;
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (b0 + u < a.blocks) g += v[u];
+  }
   const float m = a.beta1 * a.m[p] + (1.0f - a.beta1) * g;
   const float v = a.beta2 * a.v[p] + (1.0f - a.beta2) * g * g;
   a.m[p] = m;
