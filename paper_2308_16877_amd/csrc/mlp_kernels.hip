@@ -11,7 +11,8 @@
 //                ballot-compacted into a queue.
 //  k_mlp_fallback the exact region over the queued items.
 //  k_mlp_grad    training: forward (FP32 activations, BF16-rounded weights)
-//                and backward for 64 items per workgroup, weight-gradient
+//                and backward for 64 items per workgroup of four waves,
+//                each wave a quarter of the hidden units; weight-gradient
 //                partial sums per workgroup (deterministic, no atomics).
 //  k_mlp_adam    sums the partials and applies one Adam step to the FP32
 //                master weights.
@@ -242,78 +243,120 @@ __global__ void k_zero_int(int32_t *p) { *p = 0; }
 
 // ------------------------------------------------------------------ train
 
-__global__ void __launch_bounds__(64) k_mlp_grad(MlpGradArgs a) {
+// 64 items per workgroup, one per lane of each of its four waves; wave w
+// computes hidden units 16w..16w+15 of each layer (the full layers meet in
+// LDS), so the work of one item is spread over four SIMDs.  Every value is
+// formed in the same order as by a single lane computing the whole item:
+// each wave forms the network's output itself from the LDS copy of the
+// second hidden layer.
+__global__ void __launch_bounds__(256) k_mlp_grad(MlpGradArgs a) {
   __shared__ float W[kNumParams];           // BF16-rounded weights, FP32 biases
   __shared__ float h1s[64][kNH + 1], h2s[64][kNH + 1], dz2s[64][kNH + 1], dz1s[64][kNH + 1];
   __shared__ float xhs[64][5], dys[64][2], errs[64];
-  const int t = threadIdx.x;
-  for (int p = t; p < kNumParams; p += 64) {
+  const int T = threadIdx.x;
+  const int w = T >> 6, t = T & 63;  // wave, and the lane's item in the workgroup
+  const int u0 = 16 * w;             // the wave's hidden units
+  for (int p = T; p < kNumParams; p += 256) {
     const bool is_bias = (p >= kOffB1 && p < kOffW2) || (p >= kOffB2 && p < kOffW3) || p >= kOffB3;
     W[p] = is_bias ? a.params[p] : round_bf16(a.params[p]);
   }
-  __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * 64 + t;
   const bool active = i < a.n;
   float xh[5];
 #pragma unroll
-  for (int j = 0; j < 5; ++j) {
-    xh[j] = active ? (a.x[j][i] - a.in_center[j]) * a.in_scale[j] : 0.0f;
-    xhs[t][j] = xh[j];
-  }
-  // forward
-  float h[kNH], z2[kNH];
+  for (int j = 0; j < 5; ++j) xh[j] = active ? (a.x[j][i] - a.in_center[j]) * a.in_scale[j] : 0.0f;
+  if (w == 0) {
 #pragma unroll
-  for (int o = 0; o < kNH; ++o) {
+    for (int j = 0; j < 5; ++j) xhs[t][j] = xh[j];
+  }
+  __syncthreads();
+  // forward, layer 1: the wave's units
+  float z1[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int o = u0 + u;
     float z = W[kOffB1 + o];
 #pragma unroll
     for (int j = 0; j < 5; ++j) z = __builtin_fmaf(W[o * 5 + j], xh[j], z);
-    h[o] = gelu(z);
-    h1s[t][o] = h[o];
+    z1[u] = z;
+    h1s[t][o] = gelu(z);
   }
+  __syncthreads();
+  // layer 2: the wave's units, from the whole first layer
+  float z2[16];
+  {
+    float h[kNH];
 #pragma unroll
-  for (int o = 0; o < kNH; ++o) {
-    float z = W[kOffB2 + o];
+    for (int j = 0; j < kNH; ++j) h[j] = h1s[t][j];
 #pragma unroll
-    for (int j = 0; j < kNH; ++j) z = __builtin_fmaf(W[kOffW2 + o * kNH + j], h[j], z);
-    z2[o] = z;
+    for (int u = 0; u < 16; ++u) {
+      const int o = u0 + u;
+      float z = W[kOffB2 + o];
+#pragma unroll
+      for (int j = 0; j < kNH; ++j) z = __builtin_fmaf(W[kOffW2 + o * kNH + j], h[j], z);
+      z2[u] = z;
+      h2s[t][o] = gelu(z);
+    }
   }
+  __syncthreads();
+  // layer 3, in every wave, from the whole second layer
   float yh0 = W[kOffB3], yh1 = W[kOffB3 + 1];
-#pragma unroll
+#pragma unroll 8
   for (int j = 0; j < kNH; ++j) {
-    h[j] = gelu(z2[j]);
-    h2s[t][j] = h[j];
-    yh0 = __builtin_fmaf(W[kOffW3 + j], h[j], yh0);
-    yh1 = __builtin_fmaf(W[kOffW3 + kNH + j], h[j], yh1);
+    const float h = h2s[t][j];
+    yh0 = __builtin_fmaf(W[kOffW3 + j], h, yh0);
+    yh1 = __builtin_fmaf(W[kOffW3 + kNH + j], h, yh1);
   }
   // loss 1/(2N) sum (yh - th)^2 over the N training items and both outputs
   const float e0 = active ? yh0 - (target_map(a, 0, a.t[0][i]) - a.out_mean[0]) / a.out_scale[0] : 0.0f;
   const float e1 = active ? yh1 - (target_map(a, 1, a.t[1][i]) - a.out_mean[1]) / a.out_scale[1] : 0.0f;
   const float dy0 = e0 * a.inv_count, dy1 = e1 * a.inv_count;
-  dys[t][0] = dy0;
-  dys[t][1] = dy1;
-  errs[t] = e0 * e0 + e1 * e1;
-  // backward through layer 3 and the second GELU
-#pragma unroll
-  for (int j = 0; j < kNH; ++j) {
-    const float dh = W[kOffW3 + j] * dy0 + W[kOffW3 + kNH + j] * dy1;
-    z2[j] = dh * gelu_d(z2[j]);  // now dz2
-    dz2s[t][j] = z2[j];
+  if (w == 0) {
+    dys[t][0] = dy0;
+    dys[t][1] = dy1;
+    errs[t] = e0 * e0 + e1 * e1;
   }
-  // through layer 2 and the first GELU (z1 recomputed)
-#pragma unroll 4
-  for (int j = 0; j < kNH; ++j) {
-    float dh = 0.0f;
+  // backward through layer 3 and the second GELU: the wave's units
 #pragma unroll
-    for (int o = 0; o < kNH; ++o) dh = __builtin_fmaf(W[kOffW2 + o * kNH + j], z2[o], dh);
-    float z = W[kOffB1 + j];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) z = __builtin_fmaf(W[j * 5 + k], xh[k], z);
-    dz1s[t][j] = dh * gelu_d(z);
+  for (int u = 0; u < 16; ++u) {
+    const int j = u0 + u;
+    const float dh = W[kOffW3 + j] * dy0 + W[kOffW3 + kNH + j] * dy1;
+    dz2s[t][j] = dh * gelu_d(z2[u]);
   }
   __syncthreads();
-  // per-workgroup weight gradients: thread t owns output unit t of each layer
+  // through layer 2 and the first GELU: the wave's units, from all of dz2
+  {
+    float d2[kNH];
+#pragma unroll
+    for (int o = 0; o < kNH; ++o) d2[o] = dz2s[t][o];
+#pragma unroll 4
+    for (int u = 0; u < 16; ++u) {
+      const int j = u0 + u;
+      float dh = 0.0f;
+#pragma unroll
+      for (int o = 0; o < kNH; ++o) dh = __builtin_fmaf(W[kOffW2 + o * kNH + j], d2[o], dh);
+      dz1s[t][j] = dh * gelu_d(z1[u]);
+    }
+  }
+  __syncthreads();
+  // per-workgroup weight gradients, each summed over the 64 items in order
   float *part = a.grad_partials + (int64_t)blockIdx.x * kNumParams;
   {
+    // layer 2: thread T owns output unit T / 4, input units 16 (T % 4) ..
+    const int o = T >> 2, j0 = 16 * (T & 3);
+    float acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0f;
+    for (int it = 0; it < 64; ++it) {
+      const float d2 = dz2s[it][o];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[q] = __builtin_fmaf(d2, h1s[it][j0 + q], acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) part[kOffW2 + o * kNH + j0 + q] = acc[q];
+  }
+  if (w == 0) {
+    // layer 1 and the first two biases: lane t owns unit t
     float gb1 = 0.0f, gw1[5] = {0, 0, 0, 0, 0};
     float gb2 = 0.0f;
     for (int it = 0; it < 64; ++it) {
@@ -327,22 +370,8 @@ __global__ void __launch_bounds__(64) k_mlp_grad(MlpGradArgs a) {
     for (int k = 0; k < 5; ++k) part[t * 5 + k] = gw1[k];
     part[kOffB1 + t] = gb1;
     part[kOffB2 + t] = gb2;
-  }
-#pragma unroll 1
-  for (int j0 = 0; j0 < kNH; j0 += 16) {
-    float acc[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = 0.0f;
-    for (int it = 0; it < 64; ++it) {
-      const float d2 = dz2s[it][t];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) acc[q] = __builtin_fmaf(d2, h1s[it][j0 + q], acc[q]);
-    }
-#pragma unroll
-    for (int q = 0; q < 16; ++q) part[kOffW2 + t * kNH + j0 + q] = acc[q];
-  }
-  {
-    // layer 3: 2 x 64 weights; thread t owns input unit t
+  } else if (w == 1) {
+    // layer 3: 2 x 64 weights; lane t owns input unit t
     float g0 = 0.0f, g1 = 0.0f;
     for (int it = 0; it < 64; ++it) {
       g0 = __builtin_fmaf(dys[it][0], h2s[it][t], g0);
@@ -350,16 +379,16 @@ __global__ void __launch_bounds__(64) k_mlp_grad(MlpGradArgs a) {
     }
     part[kOffW3 + t] = g0;
     part[kOffW3 + kNH + t] = g1;
-  }
-  if (t < 2) {
-    float s = 0.0f;
-    for (int it = 0; it < 64; ++it) s += dys[it][t];
-    part[kOffB3 + t] = s;
-  }
-  if (t == 0) {
-    float s = 0.0f;
-    for (int it = 0; it < 64; ++it) s += errs[it];
-    a.loss_partials[blockIdx.x] = s;
+  } else if (w == 2) {
+    if (t < 2) {
+      float s = 0.0f;
+      for (int it = 0; it < 64; ++it) s += dys[it][t];
+      part[kOffB3 + t] = s;
+    } else if (t == 2) {
+      float s = 0.0f;
+      for (int it = 0; it < 64; ++it) s += errs[it];
+      a.loss_partials[blockIdx.x] = s;
+    }
   }
 }
 
@@ -409,7 +438,7 @@ hipError_t launch_mlp_infer(const MlpArgs &a, hipStream_t stream) {
 }
 
 hipError_t launch_mlp_grad(const MlpGradArgs &a, hipStream_t stream) {
-  hipLaunchKernelGGL(k_mlp_grad, dim3((unsigned)((a.n + 63) / 64)), dim3(64), 0, stream, a);
+  hipLaunchKernelGGL(k_mlp_grad, dim3((unsigned)((a.n + 63) / 64)), dim3(256), 0, stream, a);
   return hipGetLastError();
 }
 
