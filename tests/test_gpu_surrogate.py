@@ -46,10 +46,12 @@ def dev_cols(a):
 
 
 @pytest.mark.parametrize("shift", [0.0, surrogate.PRICE_SHIFT])
-def test_training_gradient_matches_oracle(shift):
+@pytest.mark.parametrize("n", [4096, 4099])
+def test_training_gradient_matches_oracle(shift, n):
     """Loss and gradient of the GPU's training kernel against the oracle's
-    FP64 ones, on price targets and on log(price + shift) targets."""
-    n = 4096
+    FP64 ones, on price targets and on log(price + shift) targets; n = 4099
+    ends in a workgroup of three items whose other 61 lanes contribute
+    nothing."""
     x = inputs.uniform_box(n, seed=51).astype(np.float32)
     C, Pp, _, _ = oracle.bs_price(*x)
     t = np.stack([C, Pp]).astype(np.float32)
