@@ -550,7 +550,9 @@ def test_stale_lds_of_a_previous_launch_is_never_read(technique, level, tpw):
 
 def test_full_size_config_against_oracle():
     """2^24 options sorted by spot (pool 65,536): exact and each technique
-    at the launch configuration the benchmark times, against the oracle."""
+    at the launch configuration the benchmark times, against the oracle; the
+    uncounted launches the benchmark times (dense perforation among them)
+    write the counted launches' outputs bit for bit."""
     n = 1 << 24
     say("full-size inputs")
     x = inputs.portfolio(n, 65536, sort_by_spot=True)
@@ -569,7 +571,10 @@ def test_full_size_config_against_oracle():
     ora = oracle.iact(x, yv, sv, 16, 8, 0.05)
     assert np.array_equal(trace_dec(ti)[0], ora["dec"])
     check_outputs(yi, ora["out"], ora["scale"], what="iact 2^24")
-    del yi, ora
+    # the uncounted launch the benchmark times writes the same outputs
+    yu, _, _ = run("iact", xd, 2, 16, trace=False, counters=False, table_size=8, threshold=0.05)
+    assert np.array_equal(yu, yi)
+    del yi, yu, ora
     say("full-size taf")
     yt, tt, _ = run("taf", xd, 2, 16, history_size=4, prediction_size=4, rsd_threshold=0.01)
     replay_taf("2^24", yt, tt, gpu_exact_values(xd), sv, 16, 4, 4, 0.01, "wave", 256)
@@ -577,7 +582,10 @@ def test_full_size_config_against_oracle():
     compare_decisions(trace_dec(tt)[0], ora["dec"], 16, ora["fragile"], lag=1)
     mg, mo = mape_pair(ref, yt, ora["out"])
     assert abs(mg - mo) <= 1e-4
-    del yt, ora
+    yu, _, _ = run("taf", xd, 2, 16, trace=False, counters=False, history_size=4, prediction_size=4,
+                   rsd_threshold=0.01)
+    assert np.array_equal(yu, yt)
+    del yt, yu, ora
     say("full-size perfo")
     yp, tp, _ = run("perfo", xd, 2, 20, kind="small", param=10)
     ora = oracle.perfo(yv, sv, 20, 0, 10, 0, out_init=np.full_like(yv, SENTINEL))
@@ -585,3 +593,6 @@ def test_full_size_config_against_oracle():
     assert abs(skipped.mean() - 0.1) < 1e-3
     check_outputs(yp, ora["out"], ora["scale"], mask=~skipped, what="perfo 2^24")
     assert np.all(yp[:, skipped] == SENTINEL)
+    # the dense kernel the benchmark times: the same outputs, dropped items untouched
+    yu, _, _ = run("perfo", xd, 2, 20, trace=False, counters=False, kind="small", param=10)
+    assert np.array_equal(yu, yp)
